@@ -1,0 +1,61 @@
+"""Pins of the oracle's 3-d spectral derivatives (double cover, chain rule)."""
+import numpy as np
+import pytest
+
+from oracle.grid import Shell
+from oracle.derivs import d_r, d_theta, d_phi, cartesian_derivs, meridian_circle
+from paper_1104_3408_amd import inputs
+
+
+def test_double_cover_identity():
+    """The lower half of the meridian circle is f(2 pi - theta, phi + pi)
+    (Sec. 2.1): for f = x the circle through phi_j samples
+    sin(theta) cos(phi_j) at theta_0..theta_{2N-1}."""
+    sh = Shell(3, 7, 14, 1.0, 2.0)
+    x, y, z = sh.cartesian()
+    for j in (0, 3, 10):
+        circ = meridian_circle(x, j, sh)[:, 0]
+        th = np.pi * (np.arange(14) + 0.5) / 7
+        assert np.allclose(circ, sh.r[0] * np.sin(th) * np.cos(sh.phi[j]), atol=1e-14)
+
+
+def test_coordinate_derivatives_closed_form():
+    """d_theta and d_phi of x, y, z/r-type functions match the closed forms."""
+    sh = Shell(6, 9, 18, 2.0, 5.0)
+    r, th, ph = sh.coords()
+    f = r ** 2 * np.sin(th) ** 2 * np.cos(th) * np.sin(2 * ph)
+    assert np.abs(d_theta(f, sh) - r ** 2 * (2 * np.sin(th) * np.cos(th) ** 2 - np.sin(th) ** 3)
+                  * np.sin(2 * ph)).max() < 1e-12
+    assert np.abs(d_phi(f, sh) - 2 * r ** 2 * np.sin(th) ** 2 * np.cos(th) * np.cos(2 * ph)).max() < 1e-12
+    assert np.abs(d_r(f, sh) - 2 * r * np.sin(th) ** 2 * np.cos(th) * np.sin(2 * ph)).max() < 1e-11
+
+
+def test_cartesian_derivatives_of_polynomial_fields_exact():
+    """Chain rule (Sec. 2.2 eq. dvdx): for Cartesian polynomials of degree
+    below N_r and N_theta the spectral Cartesian derivative is exact."""
+    sh = Shell(12, 12, 24, 2.0, 12.0)
+    x, y, z = sh.cartesian()
+    f = np.array([x ** 3 * y - 2 * z ** 2 * x + y * z, x * y * z + z ** 4])
+    exact = [np.array([3 * x ** 2 * y - 2 * z ** 2, y * z]),
+             np.array([x ** 3 + z, x * z]),
+             np.array([-4 * z * x + y, x * y + 4 * z ** 3])]
+    got = cartesian_derivs(f, sh)
+    for i in range(3):
+        assert np.abs(got[i] - exact[i]).max() < 1e-10 * np.abs(exact[i]).max()
+
+
+def test_band_limited_inputs_differentiate_exactly():
+    """The seeded band-limited fields of the linear-operator case (12x12x24)
+    are trigonometric polynomials of degree <= 8 in theta and phi and Chebyshev
+    series of degree <= 11 in r, so every spectral derivative is exact:
+    compare against derivatives of the same fields sampled on a much finer
+    grid (brute-force resolution check at the shared points)."""
+    sh = Shell(12, 12, 24, 2.0, 12.0)
+    u = inputs.band_limited_fields(1, sh.r, sh.theta, sh.phi, 2.0, 12.0, n_v=6)
+    fine = Shell(12, 36, 72, 2.0, 12.0)      # theta_fine[3i+1] = theta_i, phi_fine[3j] = phi_j
+    uf = inputs.band_limited_fields(1, fine.r, fine.theta, fine.phi, 2.0, 12.0, n_v=6)
+    ok_th = d_theta(uf, fine)[:, ::3, 1::3, :]
+    ok_ph = d_phi(uf, fine)[:, ::3, 1::3, :]
+    assert np.allclose(fine.theta[1::3], sh.theta)
+    assert np.abs(d_theta(u, sh) - ok_th).max() < 1e-11 * np.abs(ok_th).max()
+    assert np.abs(d_phi(u, sh) - ok_ph).max() < 1e-11 * np.abs(ok_ph).max()
