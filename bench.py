@@ -1,0 +1,164 @@
+"""Throughput of the filtered RK4 step on one MI355X.
+
+Workload (default): a perturbed Kerr-Schild black hole (M = 1) on one shell
+r in [1.8, 11.8] with 33 x 32 x 64 points, 50 GHG fields, Yn filter n_f = 4
+after every step, Courant factor 4, FP64.  One step = 4 right-hand-side
+evaluations (3 derivative contractions per field, pointwise GHG rhs with the
+outer boundary operator and the RK stage update) + 1 tensor filter.
+
+Prints ONE JSON line: field-points/s = n_fields * N_r * N_theta * N_phi /
+time per step, the dominant kernel's roofline figures (its own launches timed
+with HIP events on the stream it runs on, during the timed steps), and the
+CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOADS = {
+    # name: (shells, n_fields, description)
+    "ks33": ([(33, 32, 64, 1.8, 11.8)], 50,
+             "perturbed Kerr-Schild M=1, 1 shell 33x32x64 r[1.8,11.8], 50 GHG fields, Yn n_f=4, lambda=4, FP64"),
+    "ks49": ([(49, 48, 96, 1.8, 11.8)], 50,
+             "perturbed Kerr-Schild M=1, 1 shell 49x48x96 r[1.8,11.8], 50 GHG fields, Yn n_f=4, lambda=4, FP64"),
+}
+
+
+def algorithmic_bytes(cls, n_r, n_th, n_ph, n_v, K):
+    """HBM bytes a kernel class must move per launch (FP64), per field-point
+    times the field-points of one shell."""
+    fp = n_v * n_r * n_th * n_ph
+    npts = n_r * n_th * n_ph
+    per_fp = {
+        "d_r": 16.0, "d_theta": 16.0, "d_phi": 16.0,
+        # stages read u (8), du (24), plus base/acc traffic: 48, 64, 64, 48 B -> mean 56
+        "rhs_stage": 56.0,
+        "filter_decompose": 16.0, "filter_recompose": 16.0,
+        "filter_phi_analysis": 8.0 + 8.0 * K / n_ph,
+        "filter_theta": 16.0 * K / n_ph,
+        "filter_phi_synthesis": 8.0 + 8.0 * K / n_ph,
+    }[cls]
+    extra = 16 * 8 * npts if cls == "rhs_stage" else 0   # static gauge H_a, d_i H_b
+    return per_fp * fp + extra
+
+
+def cpu_baseline(shell, g10, dt, gpu_state_after_one_step):
+    """Oracle (numpy FP64) on one filtered RK4 step of the same workload."""
+    import numpy as np
+    from oracle.grid import Shell
+    from oracle import initial_data as oid
+    from oracle.evolve import Evolution
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = 1
+    n_r, n_th, n_ph, a, b = shell
+    sh = Shell(n_r, n_th, n_ph, a, b)
+    u0 = oid.first_order_data(g10, sh)
+    H, dH = oid.static_gauge(u0, sh)
+    ev = Evolution(sh, 50, H, dH, "Yn", 4)
+    t0 = time.perf_counter()
+    ref = ev.rk4_step(u0, dt)
+    t1 = time.perf_counter()
+    fp = 50 * sh.npts
+    got = gpu_state_after_one_step.reshape(ref.shape)
+    err = np.abs(got - ref)
+    scale = np.abs(ref).max()
+    rms = float(np.sqrt(np.mean(err ** 2)) / np.sqrt(np.mean(ref ** 2)))
+    return ({"value": fp / (t1 - t0), "unit": "field-points/s", "cores": int(threads), "kind": "oracle",
+             "sample": "1 filtered RK4 step of the same shell (%dx%dx%d, 50 fields), %.1f s" % (n_r, n_th, n_ph,
+                                                                                               t1 - t0)},
+            {"max_rel": float(err.max() / scale), "rms_rel": rms, "after_steps": 1})
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="ks33", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timing", action="store_true", help="skip the per-kernel HIP events")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: shells are independent and this build has no multi-GPU path "
+              "(see the sharding note in the design document); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1104_3408_amd import shellspec as ss
+    from paper_1104_3408_amd import inputs
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    shells, n_v, desc = WORKLOADS[args.workload]
+    g = ss.ShellGrid(shells, n_fields=n_v, filter="Yn", n_f=4, courant=4.0)
+    g10 = []
+    for k in range(len(shells)):
+        r, th, ph = g.coords(k)
+        g10.append(inputs.perturbed_kerr_schild(2 + k, r, th, ph).ravel())
+    g10 = np.concatenate(g10)
+    u = torch.zeros(g.state_size, dtype=torch.float64, device="cuda")
+    g.kerr_schild_data(torch.from_numpy(g10).cuda(), u)
+    stream = torch.cuda.current_stream()
+
+    # one step for the error statement, from the same initial data
+    u1 = u.clone()
+    g.rk_step(u1, 1)
+    torch.cuda.synchronize()
+    u1_host = u1.cpu().numpy()
+    del u1
+
+    g.rk_step(u, args.warmup)
+    torch.cuda.synchronize()
+    if not args.no_timing:
+        g.enable_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.rk_step(u, args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    fp = sum(n_v * a * b * c for (a, b, c, _, _) in shells)
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = fp * args.steps / elapsed
+    finite = bool(torch.isfinite(u).all().item())
+
+    out = {"metric": "field-points/s per filtered RK4 step", "value": value, "unit": "field-points/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic", "config": {"workload": desc, "shells": [list(s) for s in shells],
+                                          "n_fields": n_v, "filter": "Yn", "n_f": 4, "courant": 4.0,
+                                          "field_points": fp, "state_finite": finite}}
+    if not args.no_timing:
+        ms, cnt = g.kernel_times()
+        kern = {c: {"total_ms": ms[i], "launches": cnt[i], "avg_us": 1e3 * ms[i] / max(cnt[i], 1)}
+                for i, c in enumerate(ss.KERNEL_CLASSES)}
+        dom = max(kern, key=lambda c: kern[c]["total_ms"])
+        n_r, n_th, n_ph = shells[0][:3]
+        K = 2 * (n_th - 1 - 4) + 1
+        byts = sum(algorithmic_bytes(dom, *s[:3], n_v, 2 * (s[1] - 1 - 4) + 1) for s in shells)
+        avg_s = kern[dom]["avg_us"] * 1e-6
+        ach = byts / avg_s / 1e9
+        out["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                           "bytes_per_launch": byts, "avg_launch_us": kern[dom]["avg_us"]}
+        out["kernels"] = kern
+        out["kernel_time_share"] = {c: kern[c]["total_ms"] / max(1e-9, 1e3 * elapsed) for c in kern}
+    if not args.no_cpu_baseline and len(shells) == 1:
+        base, err = cpu_baseline(shells[0], g10.reshape((10,) + (shells[0][2], shells[0][1], shells[0][0])),
+                                 g.info(0)[2], u1_host)
+        out["cpu_baseline"] = base
+        out["error_vs_oracle"] = err
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,521 @@
+// C-ABI entry points of libshellspec (declared in include/shellspec.h).
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "host_math.h"
+#include "internal.h"
+
+using namespace sg;
+
+namespace {
+
+thread_local std::string g_err;
+
+sg_status fail(sg_status st, const std::string& msg) {
+    g_err = msg;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(SG_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+template <class T>
+hipError_t upload(T** dst, const std::vector<T>& v) {
+    hipError_t e = hipMalloc((void**)dst, sizeof(T) * std::max<size_t>(v.size(), 1));
+    if (e != hipSuccess) return e;
+    return hipMemcpy(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice);
+}
+
+// Spatial-index count d(u^mu) of the Cartesian components (Sec. 3.5), used
+// by the graded filter.
+int spatial_degree(int mu) {
+    static const int d2[10] = {0, 1, 1, 1, 2, 2, 2, 2, 2, 2};
+    if (mu < 20) return d2[mu % 10];
+    if (mu < 50) return 1 + d2[(mu - 20) % 10];
+    return ((mu - 50) % 4 == 0) ? 0 : 1;
+}
+
+void build_groups(sg_grid* g) {
+    auto& G = g->groups;
+    G.clear();
+    const int nv = g->opt.n_fields;
+    if (g->opt.filter_kind == SG_FILTER_YN) {
+        for (int o : {0, 10}) {
+            for (int c = 0; c < 4; ++c) G.push_back({o + c, -1, 0, 1});
+            G.push_back({o + 4, o + 5, 1, 1});
+            G.push_back({o + 6, o + 7, 1, 1});
+            G.push_back({o + 8, o + 9, 2, 1});
+        }
+        for (int c = 20; c < 24; ++c) G.push_back({c, -1, 0, 1});
+        G.push_back({24, 25, 1, 1});
+        G.push_back({26, 27, 1, 1});
+        G.push_back({28, 29, 2, 1});
+        // m-row: tt tr tm tmb rr rm rmb mm mmb mbmb
+        const int spin[10] = {1, 1, 2, 0, 1, 2, 0, 3, 1, -1};
+        for (int t = 0; t < 10; ++t) G.push_back({30 + 2 * t, 31 + 2 * t, std::abs(spin[t]), spin[t] < 0 ? -1 : 1});
+        if (nv == 58)
+            for (int o : {50, 54}) {
+                G.push_back({o, -1, 0, 1});
+                G.push_back({o + 1, -1, 0, 1});
+                G.push_back({o + 2, o + 3, 1, 1});
+            }
+    } else {
+        const bool graded = g->opt.filter_kind == SG_FILTER_YG;
+        for (int mu = 0; mu < nv; ++mu) G.push_back({mu, -1, graded ? spatial_degree(mu) : 0, 1});
+    }
+}
+
+// n_f of filter matrix set s: Yn sets are spins |n| = s with the global n_f;
+// Y has one spin-0 set; Yg sets are spin 0 with n_f - s (Sec. 3.5 eq. nfofmu).
+int set_spin(const sg_grid* g, int s) { return g->opt.filter_kind == SG_FILTER_YN ? s : 0; }
+int set_nf(const sg_grid* g, int s) { return g->opt.filter_kind == SG_FILTER_YG ? g->opt.n_f - s : g->opt.n_f; }
+
+sg_status check_opts(const sg_shell_desc* shells, int n_shells, const sg_options* opt) {
+    if (!shells || n_shells <= 0 || !opt) return fail(SG_EINVAL, "shells/options missing");
+    if (opt->n_fields != 50 && opt->n_fields != 58) return fail(SG_EINVAL, "n_fields must be 50 or 58");
+    if (opt->filter_kind < 0 || opt->filter_kind > 3) return fail(SG_EINVAL, "unknown filter_kind");
+    if (opt->n_f < 0) return fail(SG_EINVAL, "n_f must be >= 0");
+    if (opt->precision != SG_PREC_FP64) return fail(SG_EUNSUPPORTED, "only SG_PREC_FP64 is built");
+    if (!(opt->courant > 0)) return fail(SG_EINVAL, "courant must be > 0");
+    for (int s = 0; s < n_shells; ++s) {
+        const auto& d = shells[s];
+        if (d.n_r < 4 || d.n_r > 80) return fail(SG_ESHAPE, "N_r must be in [4, 80]");
+        if (d.n_theta < 4 || d.n_theta > 96) return fail(SG_ESHAPE, "N_theta must be in [4, 96]");
+        if (d.n_phi != 2 * d.n_theta) return fail(SG_ESHAPE, "N_phi must equal 2 N_theta");
+        if (!(d.r_min > 0 && d.r_max > d.r_min)) return fail(SG_EINVAL, "need 0 < r_min < r_max");
+    }
+    return SG_OK;
+}
+
+void free_shell(ShellHost& s) {
+    for (double* p : {s.Dr, s.Hth, s.Dph, s.rk, s.sth, s.cth, s.sph, s.cph, s.ana, s.syn, s.fmat, s.H, s.dH})
+        if (p) (void)hipFree(p);
+}
+
+struct TimeScope {
+    sg_grid* g;
+    int cls;
+    hipStream_t st;
+    hipEvent_t e1 = nullptr;
+    TimeScope(sg_grid* g_, int c, hipStream_t s) : g(g_), cls(c), st(s) {
+        if (!g->tm.on) return;
+        hipEvent_t e0;
+        (void)hipEventCreate(&e0);
+        (void)hipEventCreate(&e1);
+        (void)hipEventRecord(e0, st);
+        g->tm.ev.push_back(e0);
+    }
+    ~TimeScope() {
+        if (!g->tm.on) return;
+        (void)hipEventRecord(e1, st);
+        g->tm.ev.push_back(e1);
+        g->tm.cls.push_back(cls);
+    }
+};
+
+size_t layout_offset(const sg_grid* g, int shell, int nfield) {
+    size_t o = 0;
+    for (int s = 0; s < shell; ++s) o += g->sh[s].npts * nfield;
+    return o;
+}
+
+// Coordinate (or Cartesian) derivatives of n_fields variables of one shell.
+hipError_t derivs_shell(sg_grid* g, int s, const double* in, double* out, int nfield, bool cart, hipStream_t st) {
+    const ShellHost& S = g->sh[s];
+    const KShell v = S.view(nfield);
+    const long long cnt = (long long)S.npts * nfield;
+    hipError_t e;
+    {
+        TimeScope ts(g, SG_K_DR, st);
+        if ((e = launch_dr(v, in, out, nfield, st)) != hipSuccess) return e;
+    }
+    {
+        TimeScope ts(g, SG_K_DTHETA, st);
+        if ((e = launch_dtheta(v, in, out + cnt, nfield, st)) != hipSuccess) return e;
+    }
+    {
+        TimeScope ts(g, SG_K_DPHI, st);
+        if ((e = launch_axis_phi(in, out + 2 * cnt, S.Dph, S.d.n_phi, S.d.n_phi,
+                                 (long long)S.d.n_theta * S.d.n_r, nfield, st)) != hipSuccess)
+            return e;
+    }
+    if (cart) return launch_chain(v, out, nfield, st);
+    return hipSuccess;
+}
+
+hipError_t filter_shell(sg_grid* g, int s, double* u, hipStream_t st) {
+    const ShellHost& S = g->sh[s];
+    const KShell v = S.view(g->opt.n_fields);
+    const long long ncol = (long long)S.d.n_theta * S.d.n_r;
+    hipError_t e;
+    double* cols = u;
+    if (g->tetrad) {
+        TimeScope ts(g, SG_K_DECOMP, st);
+        if ((e = launch_decompose(v, u, g->tcol, st)) != hipSuccess) return e;
+        cols = g->tcol;
+    }
+    {
+        TimeScope ts(g, SG_K_FANA, st);
+        if ((e = launch_axis_phi(cols, g->spec, S.ana, S.d.n_phi, S.K, ncol, g->n_cols, st)) != hipSuccess) return e;
+    }
+    {
+        TimeScope ts(g, SG_K_FTHETA, st);
+        if ((e = launch_ftheta(v, g->spec, g->spec2, S.fmat, g->d_groups, (int)g->groups.size(), S.m_keep, st)) !=
+            hipSuccess)
+            return e;
+    }
+    {
+        TimeScope ts(g, SG_K_FSYN, st);
+        if ((e = launch_axis_phi(g->spec2, cols, S.syn, S.K, S.d.n_phi, ncol, g->n_cols, st)) != hipSuccess) return e;
+    }
+    if (g->tetrad) {
+        TimeScope ts(g, SG_K_RECOMP, st);
+        return launch_recompose(v, g->tcol, u, st);
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+KShell ShellHost::view(int n_v) const {
+    KShell k;
+    k.n_r = d.n_r;
+    k.n_th = d.n_theta;
+    k.n_ph = d.n_phi;
+    k.n_v = n_v;
+    k.npts = (long long)npts;
+    k.Dr = Dr;
+    k.Hth = Hth;
+    k.Dph = Dph;
+    k.rk = rk;
+    k.sth = sth;
+    k.cth = cth;
+    k.sph = sph;
+    k.cph = cph;
+    k.H = H;
+    k.dH = dH;
+    return k;
+}
+
+extern "C" {
+
+const char* sg_last_error(void) { return g_err.c_str(); }
+
+sg_status shell_grid_create(const sg_shell_desc* shells, int n_shells, const sg_options* opt, const double* gauge_H,
+                            sg_grid** out) {
+    if (!out) return fail(SG_EINVAL, "out is NULL");
+    *out = nullptr;
+    sg_status st = check_opts(shells, n_shells, opt);
+    if (st != SG_OK) return st;
+    if (gauge_H && opt->n_fields == 58) return fail(SG_EINVAL, "gauge_H is only used by the 50-field system");
+    sg_grid* g = new sg_grid();
+    g->opt = *opt;
+    g->tetrad = opt->filter_kind == SG_FILTER_YN;
+    g->n_cols = opt->n_fields;
+    g->n_sets = opt->filter_kind == SG_FILTER_YN ? 4 : (opt->filter_kind == SG_FILTER_YG ? 4 : 1);
+    build_groups(g);
+    size_t off = 0, spec = 0;
+    auto cleanup = [&](sg_status s, const std::string& m) {
+        shell_grid_destroy(g);
+        return fail(s, m);
+    };
+    for (int s = 0; s < n_shells; ++s) {
+        ShellHost S;
+        S.d = shells[s];
+        const int nr = S.d.n_r, nt = S.d.n_theta, np_ = S.d.n_phi, L = nt - 1;
+        S.npts = size_t(nr) * nt * np_;
+        S.count = S.npts * opt->n_fields;
+        S.off = off;
+        off += S.count;
+        S.r_host = radial_points(nr, S.d.r_min, S.d.r_max);
+        S.th_host = theta_points(nt);
+        S.ph_host = phi_points(np_);
+        const double dr = S.r_host[1] - S.r_host[0];
+        const double chord = 2.0 * S.r_host[0] * std::sin(S.th_host[0]) * std::sin(M_PI / np_);
+        S.dt = opt->courant * std::min(dr, chord);
+        int min_nf = 1 << 20;
+        for (int k = 0; k < g->n_sets; ++k) min_nf = std::min(min_nf, set_nf(g, k));
+        S.m_keep = std::max(0, std::min(L, L - min_nf));
+        S.K = 2 * S.m_keep + 1;
+        spec = std::max(spec, size_t(g->n_cols) * S.K * nt * nr);
+        g->sh.push_back(S);
+        ShellHost& H = g->sh.back();
+        std::vector<double> sth(nt), cth(nt), sph(np_), cph(np_);
+        for (int i = 0; i < nt; ++i) { sth[i] = std::sin(H.th_host[i]); cth[i] = std::cos(H.th_host[i]); }
+        for (int j = 0; j < np_; ++j) { sph[j] = std::sin(H.ph_host[j]); cph[j] = std::cos(H.ph_host[j]); }
+        std::vector<double> fd = fourier_column(np_), Dph(size_t(np_) * np_);
+        for (int a = 0; a < np_; ++a)
+            for (int b = 0; b < np_; ++b) Dph[size_t(a) * np_ + b] = fd[((a - b) % np_ + np_) % np_];
+        std::vector<double> ana, syn;
+        fourier_real_matrices(np_, H.m_keep, ana, syn);
+        const size_t NN = size_t(nt) * nt;
+        std::vector<double> fm(size_t(g->n_sets) * (H.m_keep + 1) * 2 * NN, 0.0);
+        for (int k = 0; k < g->n_sets; ++k) {
+            const int n = set_spin(g, k), nf = set_nf(g, k);
+            for (int m = 0; m <= H.m_keep; ++m) {
+                std::vector<double> Fp = filter_matrix(n, m, nt, nf);
+                std::vector<double> Fm = (n == 0) ? Fp : filter_matrix(-n, m, nt, nf);
+                double* Sd = fm.data() + ((size_t(k) * (H.m_keep + 1) + m) * 2) * NN;
+                for (size_t e = 0; e < NN; ++e) {
+                    Sd[e] = 0.5 * (Fp[e] + Fm[e]);
+                    Sd[NN + e] = 0.5 * (Fp[e] - Fm[e]);
+                }
+            }
+        }
+        if (upload(&H.Dr, cheb_matrix(nr, H.d.r_min, H.d.r_max)) != hipSuccess ||
+            upload(&H.Hth, theta_half_matrix(nt)) != hipSuccess || upload(&H.Dph, Dph) != hipSuccess ||
+            upload(&H.rk, H.r_host) != hipSuccess || upload(&H.sth, sth) != hipSuccess ||
+            upload(&H.cth, cth) != hipSuccess || upload(&H.sph, sph) != hipSuccess ||
+            upload(&H.cph, cph) != hipSuccess || upload(&H.ana, ana) != hipSuccess ||
+            upload(&H.syn, syn) != hipSuccess || upload(&H.fmat, fm) != hipSuccess)
+            return cleanup(SG_ENOMEM, "device allocation/upload of operator matrices failed");
+        if (opt->n_fields == 50) {
+            if (hipMalloc((void**)&H.H, sizeof(double) * 4 * H.npts) != hipSuccess ||
+                hipMalloc((void**)&H.dH, sizeof(double) * 12 * H.npts) != hipSuccess)
+                return cleanup(SG_ENOMEM, "gauge allocation failed");
+            (void)hipMemset(H.H, 0, sizeof(double) * 4 * H.npts);
+            (void)hipMemset(H.dH, 0, sizeof(double) * 12 * H.npts);
+        }
+    }
+    g->total = off;
+    g->spec_size = spec;
+    size_t maxc = 0;
+    for (auto& S : g->sh) maxc = std::max(maxc, S.count);
+    if (hipMalloc((void**)&g->us, sizeof(double) * 2 * g->total) != hipSuccess ||
+        hipMalloc((void**)&g->acc, sizeof(double) * g->total) != hipSuccess ||
+        hipMalloc((void**)&g->dbuf, sizeof(double) * 3 * g->total) != hipSuccess ||
+        hipMalloc((void**)&g->tcol, sizeof(double) * maxc) != hipSuccess ||
+        hipMalloc((void**)&g->spec, sizeof(double) * spec) != hipSuccess ||
+        hipMalloc((void**)&g->spec2, sizeof(double) * spec) != hipSuccess ||
+        hipMalloc((void**)&g->d_flag, sizeof(int)) != hipSuccess)
+        return cleanup(SG_ENOMEM, "workspace allocation failed");
+    if (upload(&g->d_groups, g->groups) != hipSuccess) return cleanup(SG_ENOMEM, "group upload failed");
+    if (hipMemset(g->spec2, 0, sizeof(double) * spec) != hipSuccess) return cleanup(SG_EHIP, "memset failed");
+    if (gauge_H) {
+        sg_status s2 = sg_set_gauge(g, gauge_H, nullptr);
+        if (s2 != SG_OK) {
+            std::string m = g_err;
+            return cleanup(s2, m);
+        }
+        if (hipDeviceSynchronize() != hipSuccess) return cleanup(SG_EHIP, "gauge setup failed");
+    }
+    *out = g;
+    return SG_OK;
+}
+
+void shell_grid_destroy(sg_grid* g) {
+    if (!g) return;
+    for (auto& s : g->sh) free_shell(s);
+    for (void* p : {(void*)g->us, (void*)g->acc, (void*)g->dbuf, (void*)g->tcol, (void*)g->spec, (void*)g->spec2,
+                    (void*)g->d_flag, (void*)g->d_groups})
+        if (p) (void)hipFree(p);
+    for (auto e : g->tm.ev) (void)hipEventDestroy(e);
+    delete g;
+}
+
+sg_status shell_grid_info(const sg_grid* g, int shell, size_t* offset, size_t* count, double* dt) {
+    if (!g) return fail(SG_EINVAL, "grid is NULL");
+    if (shell == -1) {
+        double m = 1e300;
+        for (auto& s : g->sh) m = std::min(m, s.dt);
+        if (offset) *offset = 0;
+        if (count) *count = g->total;
+        if (dt) *dt = m;
+        return SG_OK;
+    }
+    if (shell < 0 || shell >= (int)g->sh.size()) return fail(SG_EINVAL, "shell index out of range");
+    if (offset) *offset = g->sh[shell].off;
+    if (count) *count = g->sh[shell].count;
+    if (dt) *dt = g->sh[shell].dt;
+    return SG_OK;
+}
+
+sg_status shell_grid_coords(const sg_grid* g, int shell, double* r, double* theta, double* phi) {
+    if (!g) return fail(SG_EINVAL, "grid is NULL");
+    if (shell < 0 || shell >= (int)g->sh.size()) return fail(SG_EINVAL, "shell index out of range");
+    const ShellHost& S = g->sh[shell];
+    if (r) std::memcpy(r, S.r_host.data(), sizeof(double) * S.r_host.size());
+    if (theta) std::memcpy(theta, S.th_host.data(), sizeof(double) * S.th_host.size());
+    if (phi) std::memcpy(phi, S.ph_host.data(), sizeof(double) * S.ph_host.size());
+    return SG_OK;
+}
+
+sg_status sg_set_gauge(sg_grid* g, const double* H, sg_stream_t stream) {
+    if (!g || !H) return fail(SG_EINVAL, "grid or H is NULL");
+    if (g->opt.n_fields != 50) return fail(SG_EINVAL, "the 58-field system evolves its gauge source");
+    hipStream_t st = (hipStream_t)stream;
+    for (int s = 0; s < (int)g->sh.size(); ++s) {
+        ShellHost& S = g->sh[s];
+        const double* src = H + layout_offset(g, s, 4);
+        HIP_TRY(hipMemcpyAsync(S.H, src, sizeof(double) * 4 * S.npts, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(derivs_shell(g, s, S.H, g->dbuf, 4, true, st));
+        HIP_TRY(hipMemcpyAsync(S.dH, g->dbuf, sizeof(double) * 12 * S.npts, hipMemcpyDeviceToDevice, st));
+    }
+    return SG_OK;
+}
+
+sg_status spec_derivs(sg_grid* g, const double* u, double* du, int mode, sg_stream_t stream) {
+    if (!g || !u || !du) return fail(SG_EINVAL, "NULL argument");
+    if (mode != SG_COORD && mode != SG_CART) return fail(SG_EINVAL, "mode must be SG_COORD or SG_CART");
+    if ((const double*)du == u) return fail(SG_EINVAL, "du must not alias u");
+    hipStream_t st = (hipStream_t)stream;
+    for (int s = 0; s < (int)g->sh.size(); ++s) {
+        const ShellHost& S = g->sh[s];
+        HIP_TRY(derivs_shell(g, s, u + S.off, du + 3 * S.off, g->opt.n_fields, mode == SG_CART, st));
+    }
+    return SG_OK;
+}
+
+sg_status swsh_filter(sg_grid* g, double* u, sg_stream_t stream) {
+    if (!g || !u) return fail(SG_EINVAL, "NULL argument");
+    if (g->opt.filter_kind == SG_FILTER_NONE) return SG_OK;
+    hipStream_t st = (hipStream_t)stream;
+    for (int s = 0; s < (int)g->sh.size(); ++s) HIP_TRY(filter_shell(g, s, u + g->sh[s].off, st));
+    return SG_OK;
+}
+
+sg_status ghg_rhs(sg_grid* g, const double* u, const double* du_cart, double* rhs, sg_stream_t stream) {
+    if (!g || !u || !rhs) return fail(SG_EINVAL, "NULL argument");
+    if ((const double*)rhs == u) return fail(SG_EINVAL, "rhs must not alias u");
+    hipStream_t st = (hipStream_t)stream;
+    for (int s = 0; s < (int)g->sh.size(); ++s) {
+        const ShellHost& S = g->sh[s];
+        const KShell v = S.view(g->opt.n_fields);
+        const double* d = du_cart ? du_cart + 3 * S.off : g->dbuf;
+        if (!du_cart) HIP_TRY(derivs_shell(g, s, u + S.off, g->dbuf, g->opt.n_fields, false, st));
+        TimeScope ts(g, SG_K_RHS, st);
+        HIP_TRY(launch_rhs(v, u + S.off, d, du_cart != nullptr, rhs + S.off, nullptr, nullptr, 0.0, 0, st));
+    }
+    return SG_OK;
+}
+
+sg_status rk_step(sg_grid* g, double* u, const double* dt, int n_steps, sg_stream_t stream) {
+    if (!g || !u) return fail(SG_EINVAL, "NULL argument");
+    if (n_steps < 0) return fail(SG_EINVAL, "n_steps must be >= 0");
+    hipStream_t st = (hipStream_t)stream;
+    if (g->tm.on) {
+        for (auto e : g->tm.ev) (void)hipEventDestroy(e);
+        g->tm.ev.clear();
+        g->tm.cls.clear();
+    }
+    const int nv = g->opt.n_fields;
+    double* usA = g->us;
+    double* usB = g->us + g->total;
+    for (int n = 0; n < n_steps; ++n) {
+        for (int s = 0; s < (int)g->sh.size(); ++s) {
+            const ShellHost& S = g->sh[s];
+            const KShell v = S.view(nv);
+            const double h = dt ? dt[s] : S.dt;
+            double* u0 = u + S.off;
+            double* a = usA + S.off;
+            double* b = usB + S.off;
+            double* ac = g->acc + S.off;
+            // stage inputs u -> a -> b -> a, output u
+            const double* in[4] = {u0, a, b, a};
+            double* outp[4] = {a, b, a, u0};
+            for (int stage = 1; stage <= 4; ++stage) {
+                HIP_TRY(derivs_shell(g, s, in[stage - 1], g->dbuf, nv, false, st));
+                TimeScope ts(g, SG_K_RHS, st);
+                HIP_TRY(launch_rhs(v, in[stage - 1], g->dbuf, false, outp[stage - 1], u0, ac, h, stage, st));
+            }
+            if (g->opt.filter_kind != SG_FILTER_NONE) HIP_TRY(filter_shell(g, s, u0, st));
+        }
+    }
+    if (g->opt.flags & SG_CHECK_FINITE) {
+        HIP_TRY(hipMemsetAsync(g->d_flag, 0, sizeof(int), st));
+        HIP_TRY(launch_finite_check(u, g->total, g->d_flag, st));
+        int flag = 0;
+        HIP_TRY(hipMemcpyAsync(&flag, g->d_flag, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (flag) return fail(SG_ENONFINITE, "state contains NaN or Inf");
+    }
+    return SG_OK;
+}
+
+sg_status sg_kerr_schild_data(sg_grid* g, const double* g10, const double* extra8, double* u, double* H_out,
+                              sg_stream_t stream) {
+    if (!g || !g10 || !u) return fail(SG_EINVAL, "NULL argument");
+    hipStream_t st = (hipStream_t)stream;
+    const int nv = g->opt.n_fields;
+    for (int s = 0; s < (int)g->sh.size(); ++s) {
+        ShellHost& S = g->sh[s];
+        const KShell v = S.view(nv);
+        const double* gs = g10 + layout_offset(g, s, 10);
+        double* us = u + S.off;
+        if (nv == 58) {
+            if (extra8)
+                HIP_TRY(hipMemcpyAsync(us + 50 * S.npts, extra8 + layout_offset(g, s, 8), sizeof(double) * 8 * S.npts,
+                                       hipMemcpyDeviceToDevice, st));
+            else
+                HIP_TRY(hipMemsetAsync(us + 50 * S.npts, 0, sizeof(double) * 8 * S.npts, st));
+        }
+        HIP_TRY(derivs_shell(g, s, gs, g->dbuf, 10, true, st));
+        HIP_TRY(launch_initial(v, gs, g->dbuf, us, nv == 50 ? S.H : nullptr, st));
+        if (nv == 50) {
+            HIP_TRY(derivs_shell(g, s, S.H, g->dbuf, 4, true, st));
+            HIP_TRY(hipMemcpyAsync(S.dH, g->dbuf, sizeof(double) * 12 * S.npts, hipMemcpyDeviceToDevice, st));
+            if (H_out)
+                HIP_TRY(hipMemcpyAsync(H_out + layout_offset(g, s, 4), S.H, sizeof(double) * 4 * S.npts,
+                                       hipMemcpyDeviceToDevice, st));
+        }
+    }
+    return SG_OK;
+}
+
+sg_status sg_enable_timing(sg_grid* g, int on) {
+    if (!g) return fail(SG_EINVAL, "grid is NULL");
+    g->tm.on = on != 0;
+    return SG_OK;
+}
+
+sg_status sg_kernel_times(sg_grid* g, double* ms, int* counts, int n_classes) {
+    if (!g || !ms) return fail(SG_EINVAL, "NULL argument");
+    for (int c = 0; c < SG_K_COUNT; ++c) {
+        g->tm.ms[c] = 0;
+        g->tm.cnt[c] = 0;
+    }
+    if (!g->tm.ev.empty()) HIP_TRY(hipEventSynchronize(g->tm.ev.back()));
+    for (size_t k = 0; k < g->tm.cls.size(); ++k) {
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, g->tm.ev[2 * k], g->tm.ev[2 * k + 1]));
+        g->tm.ms[g->tm.cls[k]] += t;
+        g->tm.cnt[g->tm.cls[k]] += 1;
+    }
+    for (int c = 0; c < n_classes && c < SG_K_COUNT; ++c) {
+        ms[c] = g->tm.ms[c];
+        if (counts) counts[c] = g->tm.cnt[c];
+    }
+    return SG_OK;
+}
+
+// Host-only helpers (no device work): the operator matrices the library
+// builds, for comparison against an independent construction.
+int sg_host_filter_matrix(int n, int m, int n_theta, int n_f, double* out) {
+    if (!out || n_theta < 2 || n_theta > 96 || n < -3 || n > 3) return SG_EINVAL;
+    std::vector<double> F = filter_matrix(n, m, n_theta, n_f);
+    std::memcpy(out, F.data(), sizeof(double) * F.size());
+    return SG_OK;
+}
+
+int sg_host_cheb_matrix(int n_r, double r_min, double r_max, double* out) {
+    if (!out || n_r < 2) return SG_EINVAL;
+    std::vector<double> D = cheb_matrix(n_r, r_min, r_max);
+    std::memcpy(out, D.data(), sizeof(double) * D.size());
+    return SG_OK;
+}
+
+int sg_host_theta_matrix(int n_theta, double* out) {
+    if (!out || n_theta < 2) return SG_EINVAL;
+    std::vector<double> H = theta_half_matrix(n_theta);
+    std::memcpy(out, H.data(), sizeof(double) * H.size());
+    return SG_OK;
+}
+
+}  // extern "C"

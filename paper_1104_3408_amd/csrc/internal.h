@@ -1,0 +1,89 @@
+// Internal definitions shared by the HIP translation units of libshellspec.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <string>
+#include <vector>
+
+#include "shellspec.h"
+
+namespace sg {
+
+// Kernel-side view of one shell (passed by value).
+struct KShell {
+    int n_r, n_th, n_ph, n_v;
+    long long npts;           // N_r N_theta N_phi
+    const double* Dr;         // N_r x N_r, row-major
+    const double* Hth;        // N_theta x 2 N_theta folded theta matrix
+    const double* Dph;        // N_phi x N_phi
+    const double* rk;         // radii
+    const double* sth; const double* cth;   // sin, cos theta_i
+    const double* sph; const double* cph;   // sin, cos phi_j
+    const double* H;          // static gauge H_a, [4][npts]
+    const double* dH;         // Cartesian d_i H_b, [3][4][npts]
+};
+
+// One group of filter columns: a real column (im < 0) or the real and
+// imaginary storage columns of a complex tetrad component.
+struct FiltGroup {
+    int re, im, set, sign;
+};
+
+struct ShellHost {
+    sg_shell_desc d;
+    size_t off = 0, count = 0, npts = 0;
+    double dt = 0;
+    int m_keep = 0, K = 0;
+    double *Dr = nullptr, *Hth = nullptr, *Dph = nullptr;
+    double *rk = nullptr, *sth = nullptr, *cth = nullptr, *sph = nullptr, *cph = nullptr;
+    double *ana = nullptr, *syn = nullptr;   // K x N_phi, N_phi x K
+    double *fmat = nullptr;                  // [set][m = 0..m_keep][S|D][N_theta][N_theta]
+    double *H = nullptr, *dH = nullptr;      // static gauge
+    std::vector<double> r_host, th_host, ph_host;
+    KShell view(int n_v) const;
+};
+
+struct Timing {
+    bool on = false;
+    std::vector<hipEvent_t> ev;   // pairs (start, stop)
+    std::vector<int> cls;
+    double ms[SG_K_COUNT] = {};
+    int cnt[SG_K_COUNT] = {};
+};
+
+}  // namespace sg
+
+struct sg_grid {
+    sg_options opt{};
+    std::vector<sg::ShellHost> sh;
+    size_t total = 0;                 // state size in doubles
+    int n_sets = 0;
+    std::vector<sg::FiltGroup> groups;
+    sg::FiltGroup* d_groups = nullptr;
+    int n_cols = 0;                   // filter storage columns (= n_fields)
+    bool tetrad = false;              // Yn: decompose on the tetrad
+    double *us = nullptr, *acc = nullptr, *dbuf = nullptr;   // RK and derivative workspaces
+    double *tcol = nullptr, *spec = nullptr, *spec2 = nullptr;  // filter workspaces
+    size_t spec_size = 0;
+    int* d_flag = nullptr;
+    sg::Timing tm;
+};
+
+namespace sg {
+// Launchers (stream-ordered; return a HIP error code).
+hipError_t launch_dr(const KShell& s, const double* in, double* out, int n_fields, hipStream_t st);
+hipError_t launch_dtheta(const KShell& s, const double* in, double* out, int n_fields, hipStream_t st);
+hipError_t launch_axis_phi(const double* in, double* out, const double* W, int n_in, int n_out,
+                           long long ncol, int n_fields, hipStream_t st);
+hipError_t launch_chain(const KShell& s, double* du, int n_fields, hipStream_t st);
+hipError_t launch_rhs(const KShell& s, const double* u, const double* du, bool cart, double* out,
+                      const double* ubase, double* acc, double dt, int stage, hipStream_t st);
+hipError_t launch_decompose(const KShell& s, const double* u, double* t, hipStream_t st);
+hipError_t launch_recompose(const KShell& s, const double* t, double* u, hipStream_t st);
+hipError_t launch_ftheta(const KShell& s, const double* spec, double* spec2, const double* fmat,
+                         const FiltGroup* groups, int n_groups, int m_keep, hipStream_t st);
+hipError_t launch_initial(const KShell& s, const double* g10, const double* dg, double* u,
+                          double* H, hipStream_t st);
+hipError_t launch_finite_check(const double* u, size_t n, int* flag, hipStream_t st);
+}  // namespace sg
