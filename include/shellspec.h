@@ -57,11 +57,11 @@ typedef enum {
 enum { SG_FILTER_YN = 0, SG_FILTER_Y = 1, SG_FILTER_YG = 2, SG_FILTER_NONE = 3 };
 enum { SG_PREC_FP64 = 0, SG_PREC_FP32 = 1, SG_PREC_BF16X3 = 2 };
 enum { SG_COORD = 0, SG_CART = 1 };
-enum { SG_CHECK_FINITE = 1u };
+enum { SG_CHECK_FINITE = 1u, SG_NO_GRAPH = 2u };
 
 /* One shell: N_r Chebyshev points on [r_min, r_max], N_theta x N_phi angles
  * (Sec. 2.1).  Requirements checked by shell_grid_create: 4 <= N_r <= 80,
- * 4 <= N_theta <= 96, N_phi = 2 N_theta, 0 < r_min < r_max. */
+ * 4 <= N_theta <= 64, N_phi = 2 N_theta, 0 < r_min < r_max. */
 typedef struct {
     int n_r, n_theta, n_phi;
     double r_min, r_max;
@@ -76,7 +76,9 @@ typedef struct {
     int precision;    /* SG_PREC_FP64; other values return SG_EUNSUPPORTED */
     double courant;   /* lambda of Delta t = lambda min(Delta x) (Sec. 4.1), e.g. 4 */
     double mass;      /* black-hole mass M used by sg_kerr_schild_data */
-    unsigned flags;   /* SG_CHECK_FINITE: rk_step reports NaN/Inf */
+    unsigned flags;   /* SG_CHECK_FINITE: rk_step reports NaN/Inf; SG_NO_GRAPH: rk_step
+                         launches every kernel itself instead of replaying a captured
+                         HIP graph of one step */
 } sg_options;
 
 /* Build the grid object for n_shells shells: collocation points, the 1-d
@@ -138,7 +140,10 @@ sg_status ghg_rhs(sg_grid* g, const double* u, const double* du_cart, double* rh
 /* n_steps classical RK4 steps of the method of lines (Sec. 2.5), u in place:
  * four right-hand-side evaluations (derivatives, rhs, boundary operator),
  * then the filter after each full step.  dt: host array with one time step
- * per shell, or NULL for each shell's Courant step.  With SG_CHECK_FINITE the
+ * per shell, or NULL for each shell's Courant step.  One step is captured
+ * into a HIP graph (on a private stream, re-captured when u or dt change)
+ * and replayed n_steps times on the given stream, unless SG_NO_GRAPH is set
+ * or kernel timing is enabled.  With SG_CHECK_FINITE the
  * state is scanned after the last step and SG_ENONFINITE returned (this
  * synchronises the stream). */
 sg_status rk_step(sg_grid* g, double* u, const double* dt, int n_steps, sg_stream_t stream);

@@ -61,15 +61,16 @@ def phi_points(n_phi):
 def fourier_diff_matrix(n):
     """Periodic Fourier differentiation matrix for n (even) equally spaced
     points of spacing 2 pi/n: FD_ij = (-1)^(i+j) / (2 tan((x_i-x_j)/2)),
-    FD_ii = 0 (Sec. 2.3)."""
+    FD_ii = 0 (Sec. 2.3).  On this grid (x_i - x_j)/2 = pi (i - j)/n exactly,
+    so the half-difference is formed from the integer i - j rather than from
+    two rounded coordinates."""
     if n % 2:
         raise ValueError("Fourier differentiation needs an even number of points")
-    x = 2.0 * np.pi * np.arange(n) / n
     D = np.zeros((n, n))
     for i in range(n):
         for j in range(n):
             if i != j:
-                D[i, j] = (-1.0) ** (i + j) / (2.0 * np.tan(0.5 * (x[i] - x[j])))
+                D[i, j] = (-1.0) ** (i + j) / (2.0 * np.tan(np.pi * (i - j) / n))
     return D
 
 

@@ -87,7 +87,7 @@ sg_status check_opts(const sg_shell_desc* shells, int n_shells, const sg_options
     for (int s = 0; s < n_shells; ++s) {
         const auto& d = shells[s];
         if (d.n_r < 4 || d.n_r > 80) return fail(SG_ESHAPE, "N_r must be in [4, 80]");
-        if (d.n_theta < 4 || d.n_theta > 96) return fail(SG_ESHAPE, "N_theta must be in [4, 96]");
+        if (d.n_theta < 4 || d.n_theta > 64) return fail(SG_ESHAPE, "N_theta must be in [4, 64]");
         if (d.n_phi != 2 * d.n_theta) return fail(SG_ESHAPE, "N_phi must equal 2 N_theta");
         if (!(d.r_min > 0 && d.r_max > d.r_min)) return fail(SG_EINVAL, "need 0 < r_min < r_max");
     }
@@ -95,7 +95,8 @@ sg_status check_opts(const sg_shell_desc* shells, int n_shells, const sg_options
 }
 
 void free_shell(ShellHost& s) {
-    for (double* p : {s.Dr, s.Hth, s.Dph, s.rk, s.sth, s.cth, s.sph, s.cph, s.ana, s.syn, s.fmat, s.H, s.dH})
+    for (double* p : {s.Drb, s.Hsb, s.Hab, s.dph.Wb, s.ana.Wb, s.syn.Wb, s.rk, s.sth, s.cth, s.sph, s.cph, s.fmat,
+                      s.H, s.dH})
         if (p) (void)hipFree(p);
 }
 
@@ -142,8 +143,8 @@ hipError_t derivs_shell(sg_grid* g, int s, const double* in, double* out, int nf
     }
     {
         TimeScope ts(g, SG_K_DPHI, st);
-        if ((e = launch_axis_phi(in, out + 2 * cnt, S.Dph, S.d.n_phi, S.d.n_phi,
-                                 (long long)S.d.n_theta * S.d.n_r, nfield, st)) != hipSuccess)
+        if ((e = launch_axis(S.dph, in, out + 2 * cnt, (long long)S.d.n_theta * S.d.n_r, nfield, 1, st)) !=
+            hipSuccess)
             return e;
     }
     if (cart) return launch_chain(v, out, nfield, st);
@@ -163,7 +164,7 @@ hipError_t filter_shell(sg_grid* g, int s, double* u, hipStream_t st) {
     }
     {
         TimeScope ts(g, SG_K_FANA, st);
-        if ((e = launch_axis_phi(cols, g->spec, S.ana, S.d.n_phi, S.K, ncol, g->n_cols, st)) != hipSuccess) return e;
+        if ((e = launch_axis(S.ana, cols, g->spec, ncol, g->n_cols, 0, st)) != hipSuccess) return e;
     }
     {
         TimeScope ts(g, SG_K_FTHETA, st);
@@ -173,7 +174,7 @@ hipError_t filter_shell(sg_grid* g, int s, double* u, hipStream_t st) {
     }
     {
         TimeScope ts(g, SG_K_FSYN, st);
-        if ((e = launch_axis_phi(g->spec2, cols, S.syn, S.K, S.d.n_phi, ncol, g->n_cols, st)) != hipSuccess) return e;
+        if ((e = launch_axis(S.syn, g->spec2, cols, ncol, g->n_cols, 0, st)) != hipSuccess) return e;
     }
     if (g->tetrad) {
         TimeScope ts(g, SG_K_RECOMP, st);
@@ -191,9 +192,11 @@ KShell ShellHost::view(int n_v) const {
     k.n_ph = d.n_phi;
     k.n_v = n_v;
     k.npts = (long long)npts;
-    k.Dr = Dr;
-    k.Hth = Hth;
-    k.Dph = Dph;
+    k.Drb = Drb;
+    k.Hsb = Hsb;
+    k.Hab = Hab;
+    k.Dr_R = Dr_R;
+    k.Hth_R = Hth_R;
     k.rk = rk;
     k.sth = sth;
     k.cth = cth;
@@ -269,12 +272,30 @@ sg_status shell_grid_create(const sg_shell_desc* shells, int n_shells, const sg_
                 }
             }
         }
-        if (upload(&H.Dr, cheb_matrix(nr, H.d.r_min, H.d.r_max)) != hipSuccess ||
-            upload(&H.Hth, theta_half_matrix(nt)) != hipSuccess || upload(&H.Dph, Dph) != hipSuccess ||
+        std::vector<double> Hth = theta_half_matrix(nt), Hs(size_t(nt) * nt), Ha(size_t(nt) * nt);
+        for (int a = 0; a < nt; ++a)
+            for (int b = 0; b < nt; ++b) {
+                const double hl = Hth[size_t(a) * 2 * nt + b], hr = Hth[size_t(a) * 2 * nt + nt + b];
+                Hs[size_t(a) * nt + b] = hl + hr;
+                Ha[size_t(a) * nt + b] = hl - hr;
+            }
+        int passes = 0;
+        blocked_shape(nr, H.Dr_R, passes);
+        std::vector<double> Drb = block_operator(cheb_matrix(nr, H.d.r_min, H.d.r_max), nr, nr, H.Dr_R, 1);
+        blocked_shape(nt, H.Hth_R, passes);
+        std::vector<double> Hsb = block_operator(Hs, nt, nt, H.Hth_R, 1), Hab = block_operator(Ha, nt, nt, H.Hth_R, 1);
+        auto make_axis = [&](AxisOp& op, const std::vector<double>& W, int n_out, int n_in) {
+            op.n_in = n_in;
+            op.n_out = n_out;
+            blocked_shape(n_out, op.R, op.passes);
+            return upload(&op.Wb, block_operator(W, n_out, n_in, op.R, op.passes));
+        };
+        if (upload(&H.Drb, Drb) != hipSuccess || upload(&H.Hsb, Hsb) != hipSuccess ||
+            upload(&H.Hab, Hab) != hipSuccess || make_axis(H.dph, Dph, np_, np_) != hipSuccess ||
+            make_axis(H.ana, ana, H.K, np_) != hipSuccess || make_axis(H.syn, syn, np_, H.K) != hipSuccess ||
             upload(&H.rk, H.r_host) != hipSuccess || upload(&H.sth, sth) != hipSuccess ||
             upload(&H.cth, cth) != hipSuccess || upload(&H.sph, sph) != hipSuccess ||
-            upload(&H.cph, cph) != hipSuccess || upload(&H.ana, ana) != hipSuccess ||
-            upload(&H.syn, syn) != hipSuccess || upload(&H.fmat, fm) != hipSuccess)
+            upload(&H.cph, cph) != hipSuccess || upload(&H.fmat, fm) != hipSuccess)
             return cleanup(SG_ENOMEM, "device allocation/upload of operator matrices failed");
         if (opt->n_fields == 50) {
             if (hipMalloc((void**)&H.H, sizeof(double) * 4 * H.npts) != hipSuccess ||
@@ -310,8 +331,12 @@ sg_status shell_grid_create(const sg_shell_desc* shells, int n_shells, const sg_
     return SG_OK;
 }
 
+static void drop_graph(sg_grid* g);
+
 void shell_grid_destroy(sg_grid* g) {
     if (!g) return;
+    drop_graph(g);
+    if (g->cap) (void)hipStreamDestroy(g->cap);
     for (auto& s : g->sh) free_shell(s);
     for (void* p : {(void*)g->us, (void*)g->acc, (void*)g->dbuf, (void*)g->tcol, (void*)g->spec, (void*)g->spec2,
                     (void*)g->d_flag, (void*)g->d_groups})
@@ -396,6 +421,67 @@ sg_status ghg_rhs(sg_grid* g, const double* u, const double* du_cart, double* rh
     return SG_OK;
 }
 
+// One filtered RK4 step of every shell (Sec. 2.5): stage inputs u -> a -> b -> a,
+// the fourth stage writes u; then the filter.
+static hipError_t step_launches(sg_grid* g, double* u, const double* dt, hipStream_t st) {
+    const int nv = g->opt.n_fields;
+    double* usA = g->us;
+    double* usB = g->us + g->total;
+    hipError_t e;
+    for (int s = 0; s < (int)g->sh.size(); ++s) {
+        const ShellHost& S = g->sh[s];
+        const KShell v = S.view(nv);
+        const double h = dt ? dt[s] : S.dt;
+        double* u0 = u + S.off;
+        double* a = usA + S.off;
+        double* b = usB + S.off;
+        double* ac = g->acc + S.off;
+        const double* in[4] = {u0, a, b, a};
+        double* outp[4] = {a, b, a, u0};
+        for (int stage = 1; stage <= 4; ++stage) {
+            if ((e = derivs_shell(g, s, in[stage - 1], g->dbuf, nv, false, st)) != hipSuccess) return e;
+            TimeScope ts(g, SG_K_RHS, st);
+            if ((e = launch_rhs(v, in[stage - 1], g->dbuf, false, outp[stage - 1], u0, ac, h, stage, st)) !=
+                hipSuccess)
+                return e;
+        }
+        if (g->opt.filter_kind != SG_FILTER_NONE)
+            if ((e = filter_shell(g, s, u0, st)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+static void drop_graph(sg_grid* g) {
+    if (g->sgraph.exec) (void)hipGraphExecDestroy(g->sgraph.exec);
+    if (g->sgraph.graph) (void)hipGraphDestroy(g->sgraph.graph);
+    g->sgraph = StepGraph();
+}
+
+// Capture one step on the grid's private stream and instantiate it.
+static sg_status capture_step(sg_grid* g, double* u, const std::vector<double>& dts) {
+    drop_graph(g);
+    if (!g->cap) HIP_TRY(hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal));
+    const hipError_t e = step_launches(g, u, dts.data(), g->cap);
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(g->cap, &graph);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(SG_EHIP, std::string("step capture failed: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e3 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e3 != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return fail(SG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e3));
+    }
+    g->sgraph.graph = graph;
+    g->sgraph.exec = exec;
+    g->sgraph.u = u;
+    g->sgraph.dt = dts;
+    return SG_OK;
+}
+
 sg_status rk_step(sg_grid* g, double* u, const double* dt, int n_steps, sg_stream_t stream) {
     if (!g || !u) return fail(SG_EINVAL, "NULL argument");
     if (n_steps < 0) return fail(SG_EINVAL, "n_steps must be >= 0");
@@ -405,28 +491,17 @@ sg_status rk_step(sg_grid* g, double* u, const double* dt, int n_steps, sg_strea
         g->tm.ev.clear();
         g->tm.cls.clear();
     }
-    const int nv = g->opt.n_fields;
-    double* usA = g->us;
-    double* usB = g->us + g->total;
-    for (int n = 0; n < n_steps; ++n) {
-        for (int s = 0; s < (int)g->sh.size(); ++s) {
-            const ShellHost& S = g->sh[s];
-            const KShell v = S.view(nv);
-            const double h = dt ? dt[s] : S.dt;
-            double* u0 = u + S.off;
-            double* a = usA + S.off;
-            double* b = usB + S.off;
-            double* ac = g->acc + S.off;
-            // stage inputs u -> a -> b -> a, output u
-            const double* in[4] = {u0, a, b, a};
-            double* outp[4] = {a, b, a, u0};
-            for (int stage = 1; stage <= 4; ++stage) {
-                HIP_TRY(derivs_shell(g, s, in[stage - 1], g->dbuf, nv, false, st));
-                TimeScope ts(g, SG_K_RHS, st);
-                HIP_TRY(launch_rhs(v, in[stage - 1], g->dbuf, false, outp[stage - 1], u0, ac, h, stage, st));
-            }
-            if (g->opt.filter_kind != SG_FILTER_NONE) HIP_TRY(filter_shell(g, s, u0, st));
+    std::vector<double> dts(g->sh.size());
+    for (size_t s = 0; s < g->sh.size(); ++s) dts[s] = dt ? dt[s] : g->sh[s].dt;
+    const bool graph = !g->tm.on && !(g->opt.flags & SG_NO_GRAPH) && n_steps > 0;
+    if (graph) {
+        if (!g->sgraph.exec || g->sgraph.u != u || g->sgraph.dt != dts) {
+            sg_status s2 = capture_step(g, u, dts);
+            if (s2 != SG_OK) return s2;
         }
+        for (int n = 0; n < n_steps; ++n) HIP_TRY(hipGraphLaunch(g->sgraph.exec, st));
+    } else {
+        for (int n = 0; n < n_steps; ++n) HIP_TRY(step_launches(g, u, dts.data(), st));
     }
     if (g->opt.flags & SG_CHECK_FINITE) {
         HIP_TRY(hipMemsetAsync(g->d_flag, 0, sizeof(int), st));

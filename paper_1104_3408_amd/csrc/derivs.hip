@@ -3,115 +3,189 @@
 //
 // The paper applies D_1 by one GEMM on the reshaped array and D_2, D_3 by
 // transpose -> GEMM -> transpose (eqs. D1, D2, D3).  Here every direction is a
-// strided contraction staged through LDS, with no transposes:
-//   d_r      contiguous radial lines, D_r (Chebyshev, eq. CDhat) in LDS;
-//   d_theta  one workgroup per meridian circle (phi_j, phi_j + pi): both
-//            half-planes in LDS, folded N_theta x 2 N_theta matrix of the
-//            double cover (Sec. 2.1);
-//   d_phi    one workgroup per (variable, 64 contiguous (theta, r) columns),
-//            the N_phi rows of those columns in LDS.
-// The same phi-axis kernel also applies the Fourier analysis and synthesis
-// matrices of the filter (Sec. 3.1).
+// contraction over one axis with no transposes: a workgroup stages 64
+// "columns" in LDS, one column per lane, and each wave produces a
+// wave-uniform set of output rows.  The operator entries are therefore
+// wave-uniform and come through the scalar cache into SGPRs: every FP64 FMA
+// takes one SGPR and one VGPR operand, and each LDS value feeds all the
+// wave's output rows.  (On gfx950 FP64 MFMA and FP64 vector FMA have the same
+// peak, so the FP64 path uses this vector form; it handles any N without
+// padding the data.)
+//
+// Operators are stored wave-blocked and zero-padded by the host:
+// Wb[p][w][c][r] = W[(p * 4 + w) * R + r][c] (0 past the last row), so the R
+// weights one wave needs for input c are contiguous and the inner loops carry
+// no bounds checks.
+//
+//   d_r      columns = radial lines (contiguous), tile transposed in LDS;
+//   d_theta  columns = (variable, phi_j with j < N_phi/2, r_k); the two
+//            half-planes phi_j and phi_j + pi form one meridian circle of the
+//            double cover (Sec. 2.1).  With S = f(phi_j) + f(phi_j + pi) and
+//            A = f(phi_j) - f(phi_j + pi) the folded matrix [H_L | H_R] gives
+//            d f(phi_j) = ((H_L + H_R) S + (H_L - H_R) A)/2 and
+//            d f(phi_j + pi) = ((H_L + H_R) S - (H_L - H_R) A)/2, half the
+//            work of applying the N_theta x 2 N_theta matrix to both planes;
+//   phi axis columns = (variable, theta_i, r_k), rows = phi_j.  Used for
+//            d_phi (with the column mean over phi removed first: the Fourier
+//            rows annihilate constants, and near the poles this keeps the
+//            rounding error of d_phi proportional to sin(theta), so the
+//            1/(r sin theta) of the chain rule does not amplify it) and for
+//            the Fourier analysis/synthesis matrices of the filter (Sec. 3.1).
 #include "internal.h"
 
 namespace sg {
 
 namespace {
 
-constexpr int kLines = 8;      // radial lines per workgroup in d_r (N_r <= 80: <= 56 KB LDS)
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
+// d_r: 64 lines per workgroup; wave w computes k = w R + r, r < R.
+template <int R>
 __global__ __launch_bounds__(256) void k_dr(const double* __restrict__ in, double* __restrict__ out,
-                                            const double* __restrict__ D, int n_r, long long n_lines) {
-    extern __shared__ double sm[];
-    double* sD = sm;
-    double* sU = sm + n_r * n_r;
-    const long long line0 = (long long)blockIdx.x * kLines;
-    const int nl = (int)min((long long)kLines, n_lines - line0);
-    for (int e = threadIdx.x; e < n_r * n_r; e += blockDim.x) sD[e] = D[e];
+                                            const double* __restrict__ Db, int n_r, long long n_lines) {
+    extern __shared__ double sm[];   // [n_r][64]
+    const long long line0 = (long long)blockIdx.x * 64;
+    const int nl = (int)min((long long)64, n_lines - line0);
     const double* src = in + line0 * n_r;
     const int ne = nl * n_r;
-    for (int e = threadIdx.x; e < ne; e += blockDim.x) sU[e] = src[e];
+    for (int e = threadIdx.x; e < 64 * n_r; e += 256) {
+        const int l = e / n_r, k = e - l * n_r;
+        sm[k * 64 + l] = (e < ne) ? src[e] : 0.0;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int w = wave_id();
+    const double* Dw = Db + (long long)w * n_r * R;
+    double acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = 0.0;
+    for (int kk = 0; kk < n_r; ++kk) {
+        const double v = sm[kk * 64 + lane];
+        const double* d = Dw + kk * R;
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = fma(d[r], v, acc[r]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int k = w * R + r;
+        if (k < n_r) sm[k * 64 + lane] = acc[r];
+    }
     __syncthreads();
     double* dst = out + line0 * n_r;
-    for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+    for (int e = threadIdx.x; e < ne; e += 256) {
         const int l = e / n_r, k = e - l * n_r;
-        const double* row = sD + k * n_r;
-        const double* v = sU + l * n_r;
-        double acc = 0.0;
-        for (int kk = 0; kk < n_r; ++kk) acc = fma(row[kk], v[kk], acc);
-        dst[e] = acc;
+        dst[e] = sm[k * 64 + l];
     }
 }
 
-// grid: (N_phi/2, n_fields, ceil(N_r/32)).  Output for phi_j and phi_j + pi,
-// radial indices k0 .. k0+31 of the two half-planes staged in LDS.
-constexpr int kKChunk = 32;
+// d_theta on meridian pairs.  Column c = (f * half + jp) * n_r + k; 64
+// columns per workgroup, wave w computes theta rows i = w R + r.
+template <int R>
 __global__ __launch_bounds__(256) void k_dtheta(const double* __restrict__ in, double* __restrict__ out,
-                                                const double* __restrict__ H, int n_r, int n_th, int n_ph) {
-    extern __shared__ double sm[];
-    const int jp = blockIdx.x, mu = blockIdx.y;
-    const int k0 = blockIdx.z * kKChunk;
-    const int nk = min(kKChunk, n_r - k0);
-    const int jq = jp + n_ph / 2;
+                                                const double* __restrict__ Hsb, const double* __restrict__ Hab,
+                                                int n_r, int n_th, int n_ph, long long n_cols) {
+    extern __shared__ double sm[];   // S [n_th][64], A [n_th][64]
+    double* sS = sm;
+    double* sA = sm + n_th * 64;
+    const int half = n_ph / 2;
     const long long plane = (long long)n_th * n_r;
-    const long long fbase = (long long)mu * n_ph * plane;
-    const int tile = n_th * kKChunk;
-    double* sA = sm;
-    double* sB = sm + tile;
-    const double* a = in + fbase + jp * plane + k0;
-    const double* b = in + fbase + jq * plane + k0;
-    for (int e = threadIdx.x; e < tile; e += blockDim.x) {
-        const int i = e / kKChunk, k = e - i * kKChunk;
-        const bool ok = k < nk;
-        sA[e] = ok ? a[(long long)i * n_r + k] : 0.0;
-        sB[e] = ok ? b[(long long)i * n_r + k] : 0.0;
+    const long long c0 = (long long)blockIdx.x * 64;
+    for (int e = threadIdx.x; e < n_th * 64; e += 256) {
+        const int ip = e >> 6, cl = e & 63;
+        const long long c = c0 + cl;
+        double a = 0.0, b = 0.0;
+        if (c < n_cols) {
+            const long long fj = c / n_r;
+            const int k = (int)(c - fj * n_r);
+            const long long f = fj / half;
+            const int jp = (int)(fj - f * half);
+            const double* base = in + f * n_ph * plane + (long long)ip * n_r + k;
+            a = base[jp * plane];
+            b = base[(jp + half) * plane];
+        }
+        sS[e] = a + b;
+        sA[e] = a - b;
     }
     __syncthreads();
-    const int n2 = 2 * n_th;
-    double* oa = out + fbase + jp * plane + k0;
-    double* ob = out + fbase + jq * plane + k0;
-    for (int e = threadIdx.x; e < tile; e += blockDim.x) {
-        const int i = e / kKChunk, k = e - i * kKChunk;
-        if (k >= nk) continue;
-        const double* h = H + (long long)i * n2;
-        double accA = 0.0, accB = 0.0;
-        for (int ip = 0; ip < n_th; ++ip) {
-            const double h1 = h[ip], h2 = h[n_th + ip];
-            const double va = sA[ip * kKChunk + k], vb = sB[ip * kKChunk + k];
-            accA = fma(h1, va, fma(h2, vb, accA));
-            accB = fma(h1, vb, fma(h2, va, accB));
+    const int lane = threadIdx.x & 63;
+    const int w = wave_id();
+    const double* Sw = Hsb + (long long)w * n_th * R;
+    const double* Aw = Hab + (long long)w * n_th * R;
+    double aS[R], aA[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) aS[r] = aA[r] = 0.0;
+    for (int ip = 0; ip < n_th; ++ip) {
+        const double sv = sS[ip * 64 + lane], av = sA[ip * 64 + lane];
+        const double* hs = Sw + ip * R;
+        const double* ha = Aw + ip * R;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            aS[r] = fma(hs[r], sv, aS[r]);
+            aA[r] = fma(ha[r], av, aA[r]);
         }
-        oa[(long long)i * n_r + k] = accA;
-        ob[(long long)i * n_r + k] = accB;
+    }
+    const long long c = c0 + lane;
+    if (c < n_cols) {
+        const long long fj = c / n_r;
+        const int k = (int)(c - fj * n_r);
+        const long long f = fj / half;
+        const int jp = (int)(fj - f * half);
+        double* o = out + f * n_ph * plane + jp * plane + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = w * R + r;
+            if (i < n_th) {
+                o[(long long)i * n_r] = 0.5 * (aS[r] + aA[r]);
+                o[half * plane + (long long)i * n_r] = 0.5 * (aS[r] - aA[r]);
+            }
+        }
     }
 }
 
-// out[f][q][c] = sum_r W[q][r] in[f][r][c],  c < ncol, r < n_in, q < n_out.
-// grid: (ceil(ncol/COLS), n_fields), 256 threads; the 256/COLS thread groups
-// take q = w, w + 256/COLS, ... so W is read group-uniformly.
-template <int COLS>
-__global__ __launch_bounds__(256) void k_axis_phi(const double* __restrict__ in, double* __restrict__ out,
-                                                  const double* __restrict__ W, int n_in, int n_out,
-                                                  long long ncol) {
-    extern __shared__ double sm[];
-    const long long c0 = (long long)blockIdx.x * COLS;
-    const int nc = (int)min((long long)COLS, ncol - c0);
+// out[f][q][c] = sum_r W[q][r] (in[f][r][c] - m_c),  m_c = mean of column c
+// over r if center, else 0.  grid: (ceil(ncol/64), n_fields); in pass p wave
+// w computes rows q = (p * 4 + w) * R + r.
+template <int R>
+__global__ __launch_bounds__(256) void k_axis(const double* __restrict__ in, double* __restrict__ out,
+                                              const double* __restrict__ Wb, int n_in, int n_out, int passes,
+                                              long long ncol, int center) {
+    extern __shared__ double sm[];   // [n_in][64]
+    const long long c0 = (long long)blockIdx.x * 64;
+    const int nc = (int)min((long long)64, ncol - c0);
     const int f = blockIdx.y;
     const double* src = in + (long long)f * n_in * ncol + c0;
-    for (int e = threadIdx.x; e < n_in * COLS; e += blockDim.x) {
-        const int r = e / COLS, c = e - r * COLS;
+    for (int e = threadIdx.x; e < n_in * 64; e += 256) {
+        const int r = e >> 6, c = e & 63;
         sm[e] = (c < nc) ? src[(long long)r * ncol + c] : 0.0;
     }
     __syncthreads();
-    constexpr int NG = 256 / COLS;
-    const int c = threadIdx.x % COLS;
-    const int w = threadIdx.x / COLS;
+    const int lane = threadIdx.x & 63;
+    const int w = wave_id();
+    double m = 0.0;
+    if (center) {
+        for (int r = 0; r < n_in; ++r) m += sm[r * 64 + lane];
+        m /= n_in;
+    }
     double* dst = out + (long long)f * n_out * ncol + c0;
-    for (int q = w; q < n_out; q += NG) {
-        const double* wr = W + (long long)q * n_in;
-        double acc = 0.0;
-        for (int r = 0; r < n_in; ++r) acc = fma(wr[r], sm[r * COLS + c], acc);
-        if (c < nc) dst[(long long)q * ncol + c] = acc;
+    for (int p = 0; p < passes; ++p) {
+        const double* Ww = Wb + (long long)(p * 4 + w) * n_in * R;
+        double acc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = 0.0;
+        for (int ri = 0; ri < n_in; ++ri) {
+            const double v = sm[ri * 64 + lane] - m;
+            const double* wr = Ww + ri * R;
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] = fma(wr[r], v, acc[r]);
+        }
+        if (lane < nc) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int q = (p * 4 + w) * R + r;
+                if (q < n_out) dst[(long long)q * ncol + lane] = acc[r];
+            }
+        }
     }
 }
 
@@ -138,32 +212,62 @@ __global__ __launch_bounds__(256) void k_chain(KShell s, double* __restrict__ du
 
 }  // namespace
 
+std::vector<double> block_operator(const std::vector<double>& W, int n_out, int n_in, int R, int passes) {
+    std::vector<double> Wb(size_t(passes) * 4 * n_in * R, 0.0);
+    for (int p = 0; p < passes; ++p)
+        for (int w = 0; w < 4; ++w)
+            for (int c = 0; c < n_in; ++c)
+                for (int r = 0; r < R; ++r) {
+                    const int q = (p * 4 + w) * R + r;
+                    if (q < n_out) Wb[((size_t(p) * 4 + w) * n_in + c) * R + r] = W[size_t(q) * n_in + c];
+                }
+    return Wb;
+}
+
+void blocked_shape(int n_out, int& R, int& passes) {
+    const int per = (n_out + 3) / 4;              // rows per wave
+    passes = (per + kMaxRows - 1) / kMaxRows;
+    R = (per + passes - 1) / passes;
+}
+
+#define SG_R_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) \
+    X(17) X(18) X(19) X(20)
+
 hipError_t launch_dr(const KShell& s, const double* in, double* out, int n_fields, hipStream_t st) {
     const long long n_lines = (long long)n_fields * s.npts / s.n_r;
-    const unsigned blocks = (unsigned)((n_lines + kLines - 1) / kLines);
-    const size_t shm = sizeof(double) * (size_t(s.n_r) * s.n_r + size_t(kLines) * s.n_r);
-    hipLaunchKernelGGL(k_dr, dim3(blocks), dim3(256), shm, st, in, out, s.Dr, s.n_r, n_lines);
+    const unsigned blocks = (unsigned)((n_lines + 63) / 64);
+    const size_t shm = sizeof(double) * size_t(s.n_r) * 64;
+    switch (s.Dr_R) {
+#define X(R) case R: hipLaunchKernelGGL(k_dr<R>, dim3(blocks), dim3(256), shm, st, in, out, s.Drb, s.n_r, n_lines); break;
+        SG_R_CASES(X)
+#undef X
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_dtheta(const KShell& s, const double* in, double* out, int n_fields, hipStream_t st) {
-    const size_t shm = sizeof(double) * 2 * size_t(s.n_th) * kKChunk;
-    const unsigned kz = (unsigned)((s.n_r + kKChunk - 1) / kKChunk);
-    hipLaunchKernelGGL(k_dtheta, dim3(s.n_ph / 2, n_fields, kz), dim3(256), shm, st, in, out, s.Hth, s.n_r,
-                       s.n_th, s.n_ph);
+    const long long n_cols = (long long)n_fields * (s.n_ph / 2) * s.n_r;
+    const unsigned blocks = (unsigned)((n_cols + 63) / 64);
+    const size_t shm = sizeof(double) * 2 * size_t(s.n_th) * 64;
+    switch (s.Hth_R) {
+#define X(R) case R: hipLaunchKernelGGL(k_dtheta<R>, dim3(blocks), dim3(256), shm, st, in, out, s.Hsb, s.Hab, s.n_r, s.n_th, s.n_ph, n_cols); break;
+        SG_R_CASES(X)
+#undef X
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_axis_phi(const double* in, double* out, const double* W, int n_in, int n_out,
-                           long long ncol, int n_fields, hipStream_t st) {
-    if (n_in <= 128) {
-        const unsigned bx = (unsigned)((ncol + 63) / 64);
-        hipLaunchKernelGGL(k_axis_phi<64>, dim3(bx, n_fields), dim3(256), sizeof(double) * size_t(n_in) * 64, st,
-                           in, out, W, n_in, n_out, ncol);
-    } else {
-        const unsigned bx = (unsigned)((ncol + 31) / 32);
-        hipLaunchKernelGGL(k_axis_phi<32>, dim3(bx, n_fields), dim3(256), sizeof(double) * size_t(n_in) * 32, st,
-                           in, out, W, n_in, n_out, ncol);
+hipError_t launch_axis(const AxisOp& op, const double* in, double* out, long long ncol, int n_fields, int center,
+                       hipStream_t st) {
+    const unsigned bx = (unsigned)((ncol + 63) / 64);
+    const size_t shm = sizeof(double) * size_t(op.n_in) * 64;
+    switch (op.R) {
+#define X(R) case R: hipLaunchKernelGGL(k_axis<R>, dim3(bx, n_fields), dim3(256), shm, st, in, out, op.Wb, op.n_in, op.n_out, op.passes, ncol, center); break;
+        SG_R_CASES(X)
+#undef X
+        default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

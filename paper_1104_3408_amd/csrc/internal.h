@@ -14,9 +14,10 @@ namespace sg {
 struct KShell {
     int n_r, n_th, n_ph, n_v;
     long long npts;           // N_r N_theta N_phi
-    const double* Dr;         // N_r x N_r, row-major
-    const double* Hth;        // N_theta x 2 N_theta folded theta matrix
-    const double* Dph;        // N_phi x N_phi
+    const double* Drb;        // Chebyshev D_r, wave-blocked (see block_operator)
+    const double* Hsb;        // H_L + H_R of the folded theta matrix, wave-blocked
+    const double* Hab;        // H_L - H_R, wave-blocked
+    int Dr_R, Hth_R;          // rows per wave of the blocked d_r / d_theta operators
     const double* rk;         // radii
     const double* sth; const double* cth;   // sin, cos theta_i
     const double* sph; const double* cph;   // sin, cos phi_j
@@ -30,18 +31,36 @@ struct FiltGroup {
     int re, im, set, sign;
 };
 
+// A matrix applied along the phi axis (n_out x n_in), wave-blocked.
+struct AxisOp {
+    double* Wb = nullptr;
+    int n_in = 0, n_out = 0, R = 0, passes = 0;
+};
+
+// Largest number of output rows one wave accumulates per pass.
+constexpr int kMaxRows = 20;
+
 struct ShellHost {
     sg_shell_desc d;
     size_t off = 0, count = 0, npts = 0;
     double dt = 0;
     int m_keep = 0, K = 0;
-    double *Dr = nullptr, *Hth = nullptr, *Dph = nullptr;
+    double *Drb = nullptr, *Hsb = nullptr, *Hab = nullptr;
+    int Dr_R = 0, Hth_R = 0;
+    AxisOp dph, ana, syn;                    // d_phi, Fourier analysis, Fourier synthesis
     double *rk = nullptr, *sth = nullptr, *cth = nullptr, *sph = nullptr, *cph = nullptr;
-    double *ana = nullptr, *syn = nullptr;   // K x N_phi, N_phi x K
     double *fmat = nullptr;                  // [set][m = 0..m_keep][S|D][N_theta][N_theta]
     double *H = nullptr, *dH = nullptr;      // static gauge
     std::vector<double> r_host, th_host, ph_host;
     KShell view(int n_v) const;
+};
+
+// One captured filtered RK4 step (all shells), replayed per step.
+struct StepGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const double* u = nullptr;
+    std::vector<double> dt;
 };
 
 struct Timing {
@@ -68,14 +87,18 @@ struct sg_grid {
     size_t spec_size = 0;
     int* d_flag = nullptr;
     sg::Timing tm;
+    hipStream_t cap = nullptr;        // capture stream for the step graph
+    sg::StepGraph sgraph;
 };
 
 namespace sg {
 // Launchers (stream-ordered; return a HIP error code).
 hipError_t launch_dr(const KShell& s, const double* in, double* out, int n_fields, hipStream_t st);
 hipError_t launch_dtheta(const KShell& s, const double* in, double* out, int n_fields, hipStream_t st);
-hipError_t launch_axis_phi(const double* in, double* out, const double* W, int n_in, int n_out,
-                           long long ncol, int n_fields, hipStream_t st);
+hipError_t launch_axis(const AxisOp& op, const double* in, double* out, long long ncol, int n_fields, int center,
+                       hipStream_t st);
+std::vector<double> block_operator(const std::vector<double>& W, int n_out, int n_in, int R, int passes);
+void blocked_shape(int n_out, int& R, int& passes);
 hipError_t launch_chain(const KShell& s, double* du, int n_fields, hipStream_t st);
 hipError_t launch_rhs(const KShell& s, const double* u, const double* du, bool cart, double* out,
                       const double* ubase, double* acc, double dt, int stage, hipStream_t st);

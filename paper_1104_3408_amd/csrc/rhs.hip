@@ -3,12 +3,10 @@
 // chain rule (Sec. 2.2), the freezing-incoming boundary operator on the outer
 // sphere (App. A.3) and the RK4 stage combination (Sec. 2.5).
 //
-// One thread per grid point.  The right-hand side is linear in the
-// derivatives, so it is evaluated in two phases: first every term built from
-// the undifferentiated variables (3+1 split, inverse metrics, Christoffel
-// symbols, quadratic terms, constraint damping, gauge terms), then the
-// derivative terms, streamed variable by variable so that only the 50 (58)
-// accumulators stay live.
+// The derivative terms and the boundary operator couple only the fields of
+// one symmetric index pair ab (g_ab, Pi_ab, Phi_xab); the quadratic terms of
+// eq. Pidot for a pair need only rows a and b.  The work of a grid point is
+// therefore split by pair across the waves of a workgroup (see k_rhs).
 #include "internal.h"
 
 namespace sg {
@@ -21,44 +19,86 @@ __device__ __forceinline__ int pr(int a, int b) {
     return lo == 0 ? hi : (lo == 1 ? 3 + hi : (lo == 2 ? 5 + hi : 9));
 }
 
+// Symmetric pairs (a, b), a <= b, in storage order.
+__constant__ int kPA[10] = {0, 0, 0, 0, 1, 1, 1, 2, 2, 3};
+__constant__ int kPB[10] = {0, 1, 2, 3, 1, 2, 3, 2, 3, 3};
+
+constexpr int kPts = 64;      // grid points per workgroup
+constexpr int kWaves = 5;     // wave w owns symmetric pairs 2w and 2w+1
+
+// Workgroup = 64 consecutive grid points (one per lane) x 5 waves.  The
+// points' variables are staged in LDS ([item][lane], conflict-free); every
+// wave recomputes the 3+1 quantities in registers, a few per-point vectors
+// shared by all pairs are formed once into LDS, and then wave w evaluates
+// everything that belongs to its two symmetric pairs ab: the sources and
+// derivative terms of d_t g_ab, d_t Pi_ab and d_t Phi_xab, the boundary
+// operator (which couples only fields of one pair) and the RK4 stage update.
 template <int NV>
-__global__ __launch_bounds__(256) void k_rhs(KShell s, const double* __restrict__ u,
+__global__ __launch_bounds__(320) void k_rhs(KShell s, const double* __restrict__ u,
                                              const double* __restrict__ du, int cart,
                                              double* __restrict__ out, const double* __restrict__ ubase,
                                              double* __restrict__ acc, double dt, int stage) {
+    __shared__ double su[NV][kPts];          // state of the 64 points
+    __shared__ double sH[4][kPts];           // H_a
+    __shared__ double sdH[4][4][kPts];       // d_a H_b (a = t from the state or 0)
+    __shared__ double sdtg[10][kPts];        // d_t g_ab, eq. gdot
+    __shared__ double sC[4][kPts];           // C_a = H_a + Gamma_a
+    __shared__ double sHu[4][kPts];          // H^a = g^ab H_b
+    __shared__ double sv[12][kPts];          // n.n.Pi, (n^c Pi_cx gamma^xy)_y, n.n.Phi_x, -
+    __shared__ double swu[3][3][kPts];       // n^c Phi_x(y)c gamma^yz
+
     const long long np = s.npts;
-    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= np) return;
-    const int k = (int)(p % s.n_r);
-    const int i = (int)((p / s.n_r) % s.n_th);
-    const int j = (int)(p / ((long long)s.n_r * s.n_th));
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const long long p0 = (long long)blockIdx.x * kPts;
+    const long long p = p0 + lane;
+    const bool ok = p < np;
+    const long long blk = (long long)NV * np;
 
-    // ---- variables ---------------------------------------------------------
-    double g[4][4], P[4][4], F[3][4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = a; b < 4; ++b) {
-            const int q = pr(a, b);
-            g[a][b] = g[b][a] = u[q * np + p];
-            P[a][b] = P[b][a] = u[(10 + q) * np + p];
-#pragma unroll
-            for (int x = 0; x < 3; ++x) F[x][a][b] = F[x][b][a] = u[(20 + 10 * x + q) * np + p];
+    // ---- stage variables; points past the end get Minkowski data -----------
+    for (int e = threadIdx.x; e < NV * kPts; e += kWaves * 64) {
+        const int f = e >> 6, l = e & 63;
+        const long long q = p0 + l;
+        double v;
+        if (q < np) v = u[(long long)f * np + q];
+        else v = (f == 0) ? -1.0 : ((f == 4 || f == 7 || f == 9) ? 1.0 : 0.0);
+        su[f][l] = v;
+    }
+    if (NV == 50) {
+        for (int e = threadIdx.x; e < 16 * kPts; e += kWaves * 64) {
+            const int f = e >> 6, l = e & 63;
+            const long long q = p0 + l;
+            if (f < 4) {
+                sH[f][l] = (q < np) ? s.H[(long long)f * np + q] : 0.0;
+                sdH[0][f][l] = 0.0;                               // static gauge, eq. gauge
+            } else {
+                const int x = (f - 4) >> 2, b = (f - 4) & 3;      // Cartesian d_x H_b
+                sdH[x + 1][b][l] = (q < np) ? s.dH[(long long)(x * 4 + b) * np + q] : 0.0;
+            }
         }
+    }
+    __syncthreads();
 
-    // ---- 3+1 split (eqs. normal, abgfromgab) -------------------------------
-    const double gxx = g[1][1], gxy = g[1][2], gxz = g[1][3], gyy = g[2][2], gyz = g[2][3], gzz = g[3][3];
+    // ---- per-thread geometry and 3+1 split (eqs. normal, abgfromgab) -------
+    const int k = ok ? (int)(p % s.n_r) : 0;
+    const int i = ok ? (int)((p / s.n_r) % s.n_th) : 0;
+    const int j = ok ? (int)(p / ((long long)s.n_r * s.n_th)) : 0;
+    const double st = s.sth[i], ct = s.cth[i], sp = s.sph[j], cp = s.cph[j];
+    auto G = [&](int a, int b) -> double { return su[pr(a, b)][lane]; };
+    auto PI = [&](int a, int b) -> double { return su[10 + pr(a, b)][lane]; };
+    auto PH = [&](int x, int a, int b) -> double { return su[20 + 10 * x + pr(a, b)][lane]; };
+    const double gxx = G(1, 1), gxy = G(1, 2), gxz = G(1, 3), gyy = G(2, 2), gyz = G(2, 3), gzz = G(3, 3);
     const double cxx = gyy * gzz - gyz * gyz, cxy = gxz * gyz - gxy * gzz, cxz = gxy * gyz - gxz * gyy;
     const double cyy = gxx * gzz - gxz * gxz, cyz = gxy * gxz - gxx * gyz, czz = gxx * gyy - gxy * gxy;
     const double idet = 1.0 / (gxx * cxx + gxy * cxy + gxz * cxz);
-    double gi[3][3] = {{cxx * idet, cxy * idet, cxz * idet},
-                       {cxy * idet, cyy * idet, cyz * idet},
-                       {cxz * idet, cyz * idet, czz * idet}};
-    double bl[3] = {g[0][1], g[0][2], g[0][3]};
+    const double gi[3][3] = {{cxx * idet, cxy * idet, cxz * idet},
+                             {cxy * idet, cyy * idet, cyz * idet},
+                             {cxz * idet, cyz * idet, czz * idet}};
+    const double bl[3] = {G(0, 1), G(0, 2), G(0, 3)};
     double bu[3];
 #pragma unroll
     for (int x = 0; x < 3; ++x) bu[x] = gi[x][0] * bl[0] + gi[x][1] * bl[1] + gi[x][2] * bl[2];
-    const double al = sqrt(bu[0] * bl[0] + bu[1] * bl[1] + bu[2] * bl[2] - g[0][0]);
+    const double al = sqrt(bu[0] * bl[0] + bu[1] * bl[1] + bu[2] * bl[2] - G(0, 0));
     const double ial = 1.0 / al, ial2 = ial * ial;
     double gI[4][4];
     gI[0][0] = -ial2;
@@ -70,281 +110,240 @@ __global__ __launch_bounds__(256) void k_rhs(KShell s, const double* __restrict_
     }
     const double nu[4] = {ial, -bu[0] * ial, -bu[1] * ial, -bu[2] * ial};
     const double nl0 = -al;   // n_a = (-alpha, 0, 0, 0)
+    // Cartesian derivative of variable mu: chain rule of Sec. 2.2 (eq. dvdx)
+    // with the analytic Jacobian d(r, theta, phi)/d(x, y, z), formed here so
+    // that it is not live across the algebra.
+    auto cartd = [&](int mu, double d[3]) {
+        const long long q = (long long)mu * np + p;
+        const double d0 = du[q], d1 = du[blk + q], d2 = du[2 * blk + q];
+        if (cart) {
+            d[0] = d0; d[1] = d1; d[2] = d2;
+        } else {
+            const double ir = 1.0 / s.rk[k], irs = ir / st;
+            d[0] = st * cp * d0 + ct * cp * ir * d1 - sp * irs * d2;
+            d[1] = st * sp * d0 + ct * sp * ir * d1 + cp * irs * d2;
+            d[2] = ct * d0 - st * ir * d1;
+        }
+    };
 
-    // ---- Christoffel symbols (eq. Gamma), d_t g from eq. gdot ---------------
-    double Dg[4][4][4];   // Dg[c][a][b] = d_c g_ab
+    // ---- shared per-point quantities, phase 1 --------------------------------
+    if (w == 0) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            Dg[0][a][b] = -al * P[a][b] + bu[0] * F[0][a][b] + bu[1] * F[1][a][b] + bu[2] * F[2][a][b];
-#pragma unroll
-            for (int x = 0; x < 3; ++x) Dg[x + 1][a][b] = F[x][a][b];
+        for (int q = 0; q < 10; ++q) {
+            const int a = kPA[q], b = kPB[q];
+            sdtg[q][lane] = -al * PI(a, b) + bu[0] * PH(0, a, b) + bu[1] * PH(1, a, b) + bu[2] * PH(2, a, b);
         }
-    double Gm[4][4][4];   // Gm[c][a][b] = Gamma_cab
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) Gm[c][a][b] = 0.5 * (Dg[a][b][c] + Dg[b][a][c] - Dg[c][a][b]);
-    double Gc[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        double t = 0.0;
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) t += gI[a][b] * Gm[c][a][b];
-        Gc[c] = t;
-    }
-
-    // ---- gauge source H_a and d_a H_b ---------------------------------------
-    const long long blk = (long long)NV * np;
-    double Hl[4], dH[4][4];
-    if (NV == 58) {
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            Hl[b] = u[(50 + b) * np + p];
-            dH[0][b] = u[(54 + b) * np + p];   // d_t H_b = Q_b
-        }
-    } else {
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            Hl[b] = s.H[b * np + p];
-            dH[0][b] = 0.0;                     // static gauge (eq. gauge)
-        }
-    }
-    {
-        const double r = s.rk[k], st = s.sth[i], ct = s.cth[i], sp = s.sph[j], cp = s.cph[j];
-        const double ir = 1.0 / r, irs = 1.0 / (r * st);
-        const double J[3][3] = {{st * cp, ct * cp * ir, -sp * irs}, {st * sp, ct * sp * ir, cp * irs}, {ct, -st * ir, 0.0}};
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            if (NV == 58) {
-                const long long q = (long long)(50 + b) * np + p;
-                const double d0 = du[q], d1 = du[blk + q], d2 = du[2 * blk + q];
-                if (cart) {
-                    dH[1][b] = d0; dH[2][b] = d1; dH[3][b] = d2;
-                } else {
-#pragma unroll
-                    for (int x = 0; x < 3; ++x) dH[x + 1][b] = J[x][0] * d0 + J[x][1] * d1 + J[x][2] * d2;
-                }
-            } else {
-#pragma unroll
-                for (int x = 0; x < 3; ++x) dH[x + 1][b] = s.dH[(x * 4 + b) * np + p];
-            }
-        }
-    }
-    double Hu[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) Hu[c] = gI[c][0] * Hl[0] + gI[c][1] * Hl[1] + gI[c][2] * Hl[2] + gI[c][3] * Hl[3];
-    double C[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) C[c] = Hl[c] + Gc[c];
-    const double nC = nu[0] * C[0] + nu[1] * C[1] + nu[2] * C[2] + nu[3] * C[3];
-
-    // ---- undifferentiated terms of eq. Pidot --------------------------------
-    double rP[10], rF[3][10], rg[10];
-    {
-        // Z[x][c][b] = g^cd Phi_xbd,  W[c][b] = g^cd Pi_db
-        double Z[3][4][4], Wp[4][4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
+    } else if (w == 1) {
+        if (NV == 58) {
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                Wp[c][b] = gI[c][0] * P[0][b] + gI[c][1] * P[1][b] + gI[c][2] * P[2][b] + gI[c][3] * P[3][b];
+                sH[b][lane] = su[50 + b][lane];
+                sdH[0][b][lane] = su[54 + b][lane];              // d_t H_b = Q_b
+                double d[3] = {0.0, 0.0, 0.0};
+                if (ok) cartd(50 + b, d);
 #pragma unroll
-                for (int x = 0; x < 3; ++x)
-                    Z[x][c][b] = gI[c][0] * F[x][b][0] + gI[c][1] * F[x][b][1] + gI[c][2] * F[x][b][2] + gI[c][3] * F[x][b][3];
+                for (int x = 0; x < 3; ++x) sdH[x + 1][b][lane] = d[x];
             }
-        // Fu[y][a][c] = gamma^xy Phi_xac  (raised derivative index)
-        double Fu[3][4][4];
-#pragma unroll
-        for (int y = 0; y < 3; ++y)
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) Fu[y][a][c] = gi[y][0] * F[0][a][c] + gi[y][1] * F[1][a][c] + gi[y][2] * F[2][a][c];
-        // Gu[b][c][e] = g^cd g^ef Gamma_bdf
-        double Gh[4][4][4];
-#pragma unroll
-        for (int b = 0; b < 4; ++b)
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-#pragma unroll
-                for (int f = 0; f < 4; ++f)
-                    Gh[b][c][f] = gI[c][0] * Gm[b][0][f] + gI[c][1] * Gm[b][1][f] + gI[c][2] * Gm[b][2][f] + gI[c][3] * Gm[b][3][f];
-        // v^y = n^c Pi_cx gamma^xy
-        double vP[3];
-#pragma unroll
-        for (int x = 0; x < 3; ++x) vP[x] = nu[0] * P[0][x + 1] + nu[1] * P[1][x + 1] + nu[2] * P[2][x + 1] + nu[3] * P[3][x + 1];
-        double vu[3];
-#pragma unroll
-        for (int y = 0; y < 3; ++y) vu[y] = gi[y][0] * vP[0] + gi[y][1] * vP[1] + gi[y][2] * vP[2];
+        }
+    } else if (w == 2) {
         double nnP = 0.0;
 #pragma unroll
         for (int c = 0; c < 4; ++c)
 #pragma unroll
-            for (int d = 0; d < 4; ++d) nnP += nu[c] * nu[d] * P[c][d];
-
+            for (int d = 0; d < 4; ++d) nnP += nu[c] * nu[d] * PI(c, d);
+        sv[0][lane] = nnP;
+        double vP[3];
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int x = 0; x < 3; ++x)
+            vP[x] = nu[0] * PI(0, x + 1) + nu[1] * PI(1, x + 1) + nu[2] * PI(2, x + 1) + nu[3] * PI(3, x + 1);
 #pragma unroll
-            for (int b = a; b < 4; ++b) {
-                const int q = pr(a, b);
-                double quad = 0.0;
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-#pragma unroll
-                    for (int y = 0; y < 3; ++y) quad += Fu[y][a][c] * Z[y][c][b];
-                    quad -= P[a][c] * Wp[c][b];
-                    double gg = 0.0;
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        double ge = 0.0;
-#pragma unroll
-                        for (int f = 0; f < 4; ++f) ge += Gh[b][c][f] * gI[f][e];
-                        gg += Gm[a][c][e] * ge;
-                    }
-                    quad -= gg;
-                }
-                double nabH = 0.5 * (dH[a][b] + dH[b][a]);
-#pragma unroll
-                for (int c = 0; c < 4; ++c) nabH -= Hu[c] * Gm[c][a][b];
-                double bF = bu[0] * F[0][a][b] + bu[1] * F[1][a][b] + bu[2] * F[2][a][b];
-                double damp = -g[a][b] * nC;
-                if (b == 0) damp += C[a] * nl0;
-                if (a == 0) damp += C[b] * nl0;
-                rP[q] = 2.0 * al * quad - 2.0 * al * nabH - 0.5 * al * nnP * P[a][b]
-                        - al * (vu[0] * F[0][a][b] + vu[1] * F[1][a][b] + vu[2] * F[2][a][b])
-                        + al * damp + bF;
-                rg[q] = -al * P[a][b] + bF;
-            }
-    }
-
-    // ---- undifferentiated terms of eq. Phidot --------------------------------
-    {
-        // w[x][y] = n^c Phi_x(y)c,  wu[x][z] = w[x][y] gamma^yz
-        double nnF[3], wu[3][3];
+        for (int y = 0; y < 3; ++y) sv[1 + y][lane] = gi[y][0] * vP[0] + gi[y][1] * vP[1] + gi[y][2] * vP[2];
+    } else if (w == 3) {
 #pragma unroll
         for (int x = 0; x < 3; ++x) {
             double t = 0.0;
 #pragma unroll
             for (int c = 0; c < 4; ++c)
 #pragma unroll
-                for (int d = 0; d < 4; ++d) t += nu[c] * nu[d] * F[x][c][d];
-            nnF[x] = t;
-            double w[3];
+                for (int d = 0; d < 4; ++d) t += nu[c] * nu[d] * PH(x, c, d);
+            sv[4 + x][lane] = t;
+            double wv[3];
 #pragma unroll
             for (int y = 0; y < 3; ++y)
-                w[y] = nu[0] * F[x][y + 1][0] + nu[1] * F[x][y + 1][1] + nu[2] * F[x][y + 1][2] + nu[3] * F[x][y + 1][3];
+                wv[y] = nu[0] * PH(x, y + 1, 0) + nu[1] * PH(x, y + 1, 1) + nu[2] * PH(x, y + 1, 2) + nu[3] * PH(x, y + 1, 3);
 #pragma unroll
-            for (int z = 0; z < 3; ++z) wu[x][z] = w[0] * gi[0][z] + w[1] * gi[1][z] + w[2] * gi[2][z];
+            for (int z = 0; z < 3; ++z) swu[x][z][lane] = wv[0] * gi[0][z] + wv[1] * gi[1][z] + wv[2] * gi[2][z];
         }
+    }
+    __syncthreads();
+
+    // d_c g_ab (c = t from eq. gdot, c = x: Phi) and Gamma_cab (eq. Gamma)
+    auto Dg = [&](int c, int a, int b) -> double { return c == 0 ? sdtg[pr(a, b)][lane] : PH(c - 1, a, b); };
+    auto Gam = [&](int c, int a, int b) -> double { return 0.5 * (Dg(a, b, c) + Dg(b, a, c) - Dg(c, a, b)); };
+
+    // ---- shared per-point quantities, phase 2 --------------------------------
+    if (w == 0) {
 #pragma unroll
-        for (int x = 0; x < 3; ++x)
+        for (int c = 0; c < 4; ++c) {
+            double t = 0.0;
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
-                for (int b = a; b < 4; ++b) {
-                    const int q = pr(a, b);
-                    rF[x][q] = 0.5 * al * nnF[x] * P[a][b]
-                               + al * (wu[x][0] * F[0][a][b] + wu[x][1] * F[1][a][b] + wu[x][2] * F[2][a][b])
-                               - al * F[x][a][b];
-                }
+                for (int b = 0; b < 4; ++b) t += gI[a][b] * Gam(c, a, b);
+            sC[c][lane] = sH[c][lane] + t;   // C_c = H_c + Gamma_c
+        }
+    } else if (w == 1) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            sHu[c][lane] = gI[c][0] * sH[0][lane] + gI[c][1] * sH[1][lane] + gI[c][2] * sH[2][lane] + gI[c][3] * sH[3][lane];
     }
+    __syncthreads();
+    const double nC = nu[0] * sC[0][lane] + nu[1] * sC[1][lane] + nu[2] * sC[2][lane] + nu[3] * sC[3][lane];
 
-    // ---- derivative terms, streamed ------------------------------------------
-    {
-        const double r = s.rk[k], st = s.sth[i], ct = s.cth[i], sp = s.sph[j], cp = s.cph[j];
-        const double ir = 1.0 / r, irs = 1.0 / (r * st);
-        const double J[3][3] = {{st * cp, ct * cp * ir, -sp * irs}, {st * sp, ct * sp * ir, cp * irs}, {ct, -st * ir, 0.0}};
-        auto cartd = [&](int mu, double d[3]) {
-            const long long q = (long long)mu * np + p;
-            const double d0 = du[q], d1 = du[blk + q], d2 = du[2 * blk + q];
-            if (cart) {
-                d[0] = d0; d[1] = d1; d[2] = d2;
-            } else {
+    // ---- the wave's two symmetric pairs, one after the other --------------------
+#pragma unroll 1
+    for (int h = 0; h < 2; ++h) {
+        const int q = 2 * w + h;
+        const int a = kPA[q], b = kPB[q];
+        // quadratic bracket of eq. Pidot,
+        //   g^cd (gamma^ij Phi_iac Phi_jbd - Pi_ac Pi_bd) - g^cd g^ef Gamma_ace Gamma_bdf
+        //   = Phi_xac Z_xc - Pi_ac V_c - Gamma_ace Y^ce,
+        // with Z_xc = g^cd gamma^xy Phi_ybd, V_c = g^cd Pi_bd and
+        // Y = G Gamma_b G (Gamma_b the 4x4 matrix Gamma_bdf); the row-a factors
+        // are streamed from LDS.
+        double quad = 0.0;
+        {
+            double Z[3][4], V[4];
+            {
+                double Pb[3][4], pb[4];
 #pragma unroll
-                for (int x = 0; x < 3; ++x) d[x] = J[x][0] * d0 + J[x][1] * d1 + J[x][2] * d2;
+                for (int d = 0; d < 4; ++d) {
+                    const double f0 = PH(0, b, d), f1 = PH(1, b, d), f2 = PH(2, b, d);
+#pragma unroll
+                    for (int x = 0; x < 3; ++x) Pb[x][d] = gi[x][0] * f0 + gi[x][1] * f1 + gi[x][2] * f2;
+                    pb[d] = PI(b, d);
+                }
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+#pragma unroll
+                    for (int x = 0; x < 3; ++x)
+                        Z[x][c] = gI[c][0] * Pb[x][0] + gI[c][1] * Pb[x][1] + gI[c][2] * Pb[x][2] + gI[c][3] * Pb[x][3];
+                    V[c] = gI[c][0] * pb[0] + gI[c][1] * pb[1] + gI[c][2] * pb[2] + gI[c][3] * pb[3];
+                }
             }
-        };
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int q = 0; q < 10; ++q) {
+            for (int c = 0; c < 4; ++c)
+                quad += PH(0, a, c) * Z[0][c] + PH(1, a, c) * Z[1][c] + PH(2, a, c) * Z[2][c] - PI(a, c) * V[c];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        {
+            double Y[4][4];
+            {
+                double X[4][4];   // X[d][f] = g^de Gamma_bef
+#pragma unroll
+                for (int f = 0; f < 4; ++f) {
+                    double gb[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) gb[e] = Gam(b, e, f);
+#pragma unroll
+                    for (int d = 0; d < 4; ++d)
+                        X[d][f] = gI[d][0] * gb[0] + gI[d][1] * gb[1] + gI[d][2] * gb[2] + gI[d][3] * gb[3];
+                }
+#pragma unroll
+                for (int d = 0; d < 4; ++d)
+#pragma unroll
+                    for (int c = d; c < 4; ++c)
+                        Y[d][c] = Y[c][d] = X[d][0] * gI[0][c] + X[d][1] * gI[1][c] + X[d][2] * gI[2][c] + X[d][3] * gI[3][c];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+#pragma unroll
+                for (int e = c; e < 4; ++e) quad -= (c == e ? 1.0 : 2.0) * Gam(a, c, e) * Y[c][e];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        double nabH = 0.5 * (sdH[a][b][lane] + sdH[b][a][lane]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) nabH -= sHu[c][lane] * Gam(c, a, b);
+        const double Pab = PI(a, b);
+        const double Fab[3] = {PH(0, a, b), PH(1, a, b), PH(2, a, b)};
+        const double bF = bu[0] * Fab[0] + bu[1] * Fab[1] + bu[2] * Fab[2];
+        double damp = -G(a, b) * nC;
+        if (b == 0) damp += sC[a][lane] * nl0;
+        if (a == 0) damp += sC[b][lane] * nl0;
+        // eq. Pidot, undifferentiated terms
+        double rP = 2.0 * al * quad - 2.0 * al * nabH - 0.5 * al * sv[0][lane] * Pab
+                    - al * (sv[1][lane] * Fab[0] + sv[2][lane] * Fab[1] + sv[3][lane] * Fab[2]) + al * damp + bF;
+        // eq. Phidot, undifferentiated terms
+        double rF[3];
+#pragma unroll
+        for (int x = 0; x < 3; ++x)
+            rF[x] = 0.5 * al * sv[4 + x][lane] * Pab
+                    + al * (swu[x][0][lane] * Fab[0] + swu[x][1][lane] * Fab[1] + swu[x][2][lane] * Fab[2]) - al * Fab[x];
+        // eq. gdot
+        double rg = -al * Pab + bF;
+        // derivative terms
+        if (ok) {
             double d[3];
-            cartd(q, d);                                   // d_x g_q
-            rP[q] -= bu[0] * d[0] + bu[1] * d[1] + bu[2] * d[2];
+            cartd(q, d);                                    // d_x g_ab
+            rP -= bu[0] * d[0] + bu[1] * d[1] + bu[2] * d[2];
 #pragma unroll
-            for (int x = 0; x < 3; ++x) rF[x][q] += al * d[x];
-            cartd(10 + q, d);                              // d_x Pi_q
-            rP[q] += bu[0] * d[0] + bu[1] * d[1] + bu[2] * d[2];
+            for (int x = 0; x < 3; ++x) rF[x] += al * d[x];
+            cartd(10 + q, d);                               // d_x Pi_ab
+            rP += bu[0] * d[0] + bu[1] * d[1] + bu[2] * d[2];
 #pragma unroll
-            for (int x = 0; x < 3; ++x) rF[x][q] -= al * d[x];
+            for (int x = 0; x < 3; ++x) rF[x] -= al * d[x];
 #pragma unroll
             for (int x = 0; x < 3; ++x) {
-                cartd(20 + 10 * x + q, d);                 // d_y Phi_xq
-                rF[x][q] += bu[0] * d[0] + bu[1] * d[1] + bu[2] * d[2];
-                rP[q] -= al * (gi[x][0] * d[0] + gi[x][1] * d[1] + gi[x][2] * d[2]);
+                cartd(20 + 10 * x + q, d);                  // d_y Phi_xab
+                rF[x] += bu[0] * d[0] + bu[1] * d[1] + bu[2] * d[2];
+                rP -= al * (gi[x][0] * d[0] + gi[x][1] * d[1] + gi[x][2] * d[2]);
             }
         }
-    }
-
-    // ---- outer boundary: freeze incoming characteristic fields (App. A.3) ----
-    if (k == s.n_r - 1) {
-        const double xh[3] = {s.sth[i] * s.cph[j], s.sth[i] * s.sph[j], s.cth[i]};
-        double su_[3];
+        // outer boundary: freeze incoming characteristic fields (App. A.3)
+        if (k == s.n_r - 1) {
+            const double xh[3] = {st * cp, st * sp, ct};
+            double su_[3];
 #pragma unroll
-        for (int x = 0; x < 3; ++x) su_[x] = gi[x][0] * xh[0] + gi[x][1] * xh[1] + gi[x][2] * xh[2];
-        const double inorm = 1.0 / sqrt(su_[0] * xh[0] + su_[1] * xh[1] + su_[2] * xh[2]);
-        double sl[3], su[3];
+            for (int x = 0; x < 3; ++x) su_[x] = gi[x][0] * xh[0] + gi[x][1] * xh[1] + gi[x][2] * xh[2];
+            const double inorm = 1.0 / sqrt(su_[0] * xh[0] + su_[1] * xh[1] + su_[2] * xh[2]);
+            const double sF = (su_[0] * rF[0] + su_[1] * rF[1] + su_[2] * rF[2]) * inorm;
+            const double wv = 0.5 * (-rg + rP + sF);
+            rP = 0.5 * (rg + rP + sF);
 #pragma unroll
-        for (int x = 0; x < 3; ++x) {
-            sl[x] = xh[x] * inorm;
-            su[x] = su_[x] * inorm;
+            for (int x = 0; x < 3; ++x) rF[x] = xh[x] * inorm * wv;
         }
+        if (ok) {
+            auto emit = [&](int mu, double kv) {
+                const long long o = (long long)mu * np + p;
+                if (stage == 0) {
+                    out[o] = kv;
+                } else if (stage == 1) {        // k1 at u: acc = u + dt/6 k1, us = u + dt/2 k1
+                    const double u0 = su[mu][lane];
+                    acc[o] = u0 + dt * (1.0 / 6.0) * kv;
+                    out[o] = u0 + 0.5 * dt * kv;
+                } else if (stage == 2) {        // k2 at us: acc += dt/3 k2, us = u + dt/2 k2
+                    acc[o] += dt * (1.0 / 3.0) * kv;
+                    out[o] = ubase[o] + 0.5 * dt * kv;
+                } else if (stage == 3) {        // k3: acc += dt/3 k3, us = u + dt k3
+                    acc[o] += dt * (1.0 / 3.0) * kv;
+                    out[o] = ubase[o] + dt * kv;
+                } else {                        // k4: u = acc + dt/6 k4
+                    out[o] = acc[o] + dt * (1.0 / 6.0) * kv;
+                }
+            };
+            emit(q, rg);
+            emit(10 + q, rP);
 #pragma unroll
-        for (int q = 0; q < 10; ++q) {
-            const double sF = su[0] * rF[0][q] + su[1] * rF[1][q] + su[2] * rF[2][q];
-            const double w = 0.5 * (-rg[q] + rP[q] + sF);
-            rP[q] = 0.5 * (rg[q] + rP[q] + sF);
+            for (int x = 0; x < 3; ++x) emit(20 + 10 * x + q, rF[x]);
+            if (NV == 58 && w == 4 && h == 1) {
 #pragma unroll
-            for (int x = 0; x < 3; ++x) rF[x][q] = sl[x] * w;
-        }
-    }
-
-    // ---- output / RK4 stage combination (Sec. 2.5) ---------------------------
-    auto emit = [&](int mu, double kv) {
-        const long long q = (long long)mu * np + p;
-        if (stage == 0) {
-            out[q] = kv;
-        } else if (stage == 1) {          // k1 at u: acc = u + dt/6 k1, us = u + dt/2 k1
-            const double u0 = u[q];
-            acc[q] = u0 + dt * (1.0 / 6.0) * kv;
-            out[q] = u0 + 0.5 * dt * kv;
-        } else if (stage == 2) {          // k2 at us: acc += dt/3 k2, us = u + dt/2 k2
-            acc[q] += dt * (1.0 / 3.0) * kv;
-            out[q] = ubase[q] + 0.5 * dt * kv;
-        } else if (stage == 3) {          // k3: acc += dt/3 k3, us = u + dt k3
-            acc[q] += dt * (1.0 / 3.0) * kv;
-            out[q] = ubase[q] + dt * kv;
-        } else {                          // k4: u = acc + dt/6 k4
-            out[q] = acc[q] + dt * (1.0 / 6.0) * kv;
-        }
-    };
-#pragma unroll
-    for (int q = 0; q < 10; ++q) emit(q, rg[q]);
-#pragma unroll
-    for (int q = 0; q < 10; ++q) emit(10 + q, rP[q]);
-#pragma unroll
-    for (int x = 0; x < 3; ++x)
-#pragma unroll
-        for (int q = 0; q < 10; ++q) emit(20 + 10 * x + q, rF[x][q]);
-    if (NV == 58) {
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            emit(50 + b, dH[0][b]);   // d_t H_b = Q_b
-            emit(54 + b, 0.0);        // d_t Q_b = 0
+                for (int c = 0; c < 4; ++c) {
+                    emit(50 + c, sdH[0][c][lane]);   // d_t H_c = Q_c
+                    emit(54 + c, 0.0);               // d_t Q_c = 0
+                }
+            }
         }
     }
 }
@@ -420,11 +419,13 @@ __global__ __launch_bounds__(256) void k_finite(const double* __restrict__ u, si
 
 hipError_t launch_rhs(const KShell& s, const double* u, const double* du, bool cart, double* out,
                       const double* ubase, double* acc, double dt, int stage, hipStream_t st) {
-    const unsigned blocks = (unsigned)((s.npts + 255) / 256);
+    const unsigned blocks = (unsigned)((s.npts + kPts - 1) / kPts);
     if (s.n_v == 58)
-        hipLaunchKernelGGL(k_rhs<58>, dim3(blocks), dim3(256), 0, st, s, u, du, cart ? 1 : 0, out, ubase, acc, dt, stage);
+        hipLaunchKernelGGL(k_rhs<58>, dim3(blocks), dim3(kWaves * 64), 0, st, s, u, du, cart ? 1 : 0, out, ubase, acc,
+                           dt, stage);
     else
-        hipLaunchKernelGGL(k_rhs<50>, dim3(blocks), dim3(256), 0, st, s, u, du, cart ? 1 : 0, out, ubase, acc, dt, stage);
+        hipLaunchKernelGGL(k_rhs<50>, dim3(blocks), dim3(kWaves * 64), 0, st, s, u, du, cart ? 1 : 0, out, ubase, acc,
+                           dt, stage);
     return hipGetLastError();
 }
 
