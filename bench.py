@@ -118,9 +118,7 @@ def main():
 
     g.rk_step(u, args.warmup)
     torch.cuda.synchronize()
-    if not args.no_timing:
-        g.enable_timing(True)
-    torch.cuda.synchronize()
+    # timed region: K filtered steps, one captured step graph replayed per step
     t0 = time.perf_counter()
     g.rk_step(u, args.steps)
     torch.cuda.synchronize()
@@ -138,12 +136,19 @@ def main():
                                           "n_fields": n_v, "filter": "Yn", "n_f": 4, "courant": 4.0,
                                           "field_points": fp, "state_finite": finite}}
     if not args.no_timing:
+        # second timed pass of K steps with HIP events around every launch, on the
+        # stream the kernels run on (the eager launch path; events sit between launches)
+        g.enable_timing(True)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        g.rk_step(u, args.steps)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
         ms, cnt = g.kernel_times()
+        g.enable_timing(False)
         kern = {c: {"total_ms": ms[i], "launches": cnt[i], "avg_us": 1e3 * ms[i] / max(cnt[i], 1)}
                 for i, c in enumerate(ss.KERNEL_CLASSES)}
         dom = max(kern, key=lambda c: kern[c]["total_ms"])
-        n_r, n_th, n_ph = shells[0][:3]
-        K = 2 * (n_th - 1 - 4) + 1
         byts = sum(algorithmic_bytes(dom, *s[:3], n_v, 2 * (s[1] - 1 - 4) + 1) for s in shells)
         avg_s = kern[dom]["avg_us"] * 1e-6
         ach = byts / avg_s / 1e9
@@ -151,7 +156,9 @@ def main():
                            "frac": ach / HBM_PEAK_GBS, "traffic": None,
                            "bytes_per_launch": byts, "avg_launch_us": kern[dom]["avg_us"]}
         out["kernels"] = kern
-        out["kernel_time_share"] = {c: kern[c]["total_ms"] / max(1e-9, 1e3 * elapsed) for c in kern}
+        out["timing_pass_ms_per_step"] = 1e3 * (t3 - t2) / args.steps
+        tot = sum(k["total_ms"] for k in kern.values())
+        out["kernel_time_share"] = {c: kern[c]["total_ms"] / tot for c in kern}
     if not args.no_cpu_baseline and len(shells) == 1:
         base, err = cpu_baseline(shells[0], g10.reshape((10,) + (shells[0][2], shells[0][1], shells[0][0])),
                                  g.info(0)[2], u1_host)

@@ -82,7 +82,8 @@ sg_status check_opts(const sg_shell_desc* shells, int n_shells, const sg_options
     if (opt->n_fields != 50 && opt->n_fields != 58) return fail(SG_EINVAL, "n_fields must be 50 or 58");
     if (opt->filter_kind < 0 || opt->filter_kind > 3) return fail(SG_EINVAL, "unknown filter_kind");
     if (opt->n_f < 0) return fail(SG_EINVAL, "n_f must be >= 0");
-    if (opt->precision != SG_PREC_FP64) return fail(SG_EUNSUPPORTED, "only SG_PREC_FP64 is built");
+    if (opt->precision != SG_PREC_FP64 && opt->precision != SG_PREC_FP32)
+        return fail(SG_EUNSUPPORTED, "precision must be SG_PREC_FP64 or SG_PREC_FP32");
     if (!(opt->courant > 0)) return fail(SG_EINVAL, "courant must be > 0");
     for (int s = 0; s < n_shells; ++s) {
         const auto& d = shells[s];
@@ -95,8 +96,9 @@ sg_status check_opts(const sg_shell_desc* shells, int n_shells, const sg_options
 }
 
 void free_shell(ShellHost& s) {
-    for (double* p : {s.Drb, s.Hsb, s.Hab, s.dph.Wb, s.ana.Wb, s.syn.Wb, s.rk, s.sth, s.cth, s.sph, s.cph, s.fmat,
-                      s.H, s.dH})
+    for (double* p : {s.Drb, s.Hsb, s.Hab, s.dph.Wb, s.ana.Wb, s.syn.Wb, s.rk, s.sth, s.cth, s.sph, s.cph, s.fmat})
+        if (p) (void)hipFree(p);
+    for (float* p : {s.Hsb_f, s.Hab_f, s.dph.Wb_f, s.ana.Wb_f, s.syn.Wb_f})
         if (p) (void)hipFree(p);
 }
 
@@ -151,36 +153,82 @@ hipError_t derivs_shell(sg_grid* g, int s, const double* in, double* out, int nf
     return hipSuccess;
 }
 
-hipError_t filter_shell(sg_grid* g, int s, double* u, hipStream_t st) {
+// Mixed precision: d_r in FP64 into dr; d_theta, d_phi in FP32 into dang
+// (two blocks of n_fields * npts floats).
+hipError_t derivs_shell_mixed(sg_grid* g, int s, const double* in, double* dr, float* dang, int nfield,
+                              hipStream_t st) {
     const ShellHost& S = g->sh[s];
+    const KShell v = S.view(nfield);
+    const long long cnt = (long long)S.npts * nfield;
+    hipError_t e;
+    {
+        TimeScope ts(g, SG_K_DR, st);
+        if ((e = launch_dr(v, in, dr, nfield, st)) != hipSuccess) return e;
+    }
+    {
+        TimeScope ts(g, SG_K_DTHETA, st);
+        if ((e = launch_dtheta_f32(v, in, dang, nfield, st)) != hipSuccess) return e;
+    }
+    {
+        TimeScope ts(g, SG_K_DPHI, st);
+        if ((e = launch_axis_f32(S.dph, in, dang + cnt, (long long)S.d.n_theta * S.d.n_r, nfield, 1, st)) !=
+            hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
+// Filter of a run of identical shells (state of the run at u).
+hipError_t filter_run(sg_grid* g, const Run& R, double* u, hipStream_t st) {
+    const ShellHost& S = g->sh[R.first];
     const KShell v = S.view(g->opt.n_fields);
     const long long ncol = (long long)S.d.n_theta * S.d.n_r;
     hipError_t e;
     double* cols = u;
     if (g->tetrad) {
         TimeScope ts(g, SG_K_DECOMP, st);
-        if ((e = launch_decompose(v, u, g->tcol, st)) != hipSuccess) return e;
+        if ((e = launch_decompose(v, R.count, u, g->tcol, st)) != hipSuccess) return e;
         cols = g->tcol;
     }
     {
         TimeScope ts(g, SG_K_FANA, st);
-        if ((e = launch_axis(S.ana, cols, g->spec, ncol, g->n_cols, 0, st)) != hipSuccess) return e;
+        if ((e = launch_axis(S.ana, cols, g->spec, ncol, g->n_cols * R.count, 0, st)) != hipSuccess) return e;
     }
     {
         TimeScope ts(g, SG_K_FTHETA, st);
-        if ((e = launch_ftheta(v, g->spec, g->spec2, S.fmat, g->d_groups, (int)g->groups.size(), S.m_keep, st)) !=
-            hipSuccess)
+        if ((e = launch_ftheta(v, R.count, g->spec, g->spec2, S.fmat, g->d_groups, (int)g->groups.size(), g->n_cols,
+                               S.m_keep, st)) != hipSuccess)
             return e;
     }
     {
         TimeScope ts(g, SG_K_FSYN, st);
-        if ((e = launch_axis(S.syn, g->spec2, cols, ncol, g->n_cols, 0, st)) != hipSuccess) return e;
+        if ((e = launch_axis(S.syn, g->spec2, cols, ncol, g->n_cols * R.count, 0, st)) != hipSuccess) return e;
     }
     if (g->tetrad) {
         TimeScope ts(g, SG_K_RECOMP, st);
-        return launch_recompose(v, g->tcol, u, st);
+        return launch_recompose(v, R.count, g->tcol, u, st);
     }
     return hipSuccess;
+}
+
+// Runs of consecutive shells with identical grids (and, for a step, equal dt).
+std::vector<Run> make_runs(const sg_grid* g, const double* dts) {
+    std::vector<Run> runs;
+    for (int s = 0; s < (int)g->sh.size(); ++s) {
+        const sg_shell_desc& d = g->sh[s].d;
+        bool join = false;
+        if (!runs.empty()) {
+            const int f = runs.back().first;
+            const sg_shell_desc& e = g->sh[f].d;
+            join = d.n_r == e.n_r && d.n_theta == e.n_theta && d.n_phi == e.n_phi && d.r_min == e.r_min &&
+                   d.r_max == e.r_max && (!dts || dts[s] == dts[f]);
+        }
+        if (join)
+            runs.back().count++;
+        else
+            runs.push_back({s, 1});
+    }
+    return runs;
 }
 
 }  // namespace
@@ -197,6 +245,8 @@ KShell ShellHost::view(int n_v) const {
     k.Hab = Hab;
     k.Dr_R = Dr_R;
     k.Hth_R = Hth_R;
+    k.Hsb_f = Hsb_f;
+    k.Hab_f = Hab_f;
     k.rk = rk;
     k.sth = sth;
     k.cth = cth;
@@ -284,31 +334,50 @@ sg_status shell_grid_create(const sg_shell_desc* shells, int n_shells, const sg_
         std::vector<double> Drb = block_operator(cheb_matrix(nr, H.d.r_min, H.d.r_max), nr, nr, H.Dr_R, 1);
         blocked_shape(nt, H.Hth_R, passes);
         std::vector<double> Hsb = block_operator(Hs, nt, nt, H.Hth_R, 1), Hab = block_operator(Ha, nt, nt, H.Hth_R, 1);
+        auto to_f = [](const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); };
         auto make_axis = [&](AxisOp& op, const std::vector<double>& W, int n_out, int n_in) {
             op.n_in = n_in;
             op.n_out = n_out;
             blocked_shape(n_out, op.R, op.passes);
-            return upload(&op.Wb, block_operator(W, n_out, n_in, op.R, op.passes));
+            std::vector<double> Wb = block_operator(W, n_out, n_in, op.R, op.passes);
+            hipError_t e = upload(&op.Wb, Wb);
+            if (e != hipSuccess) return e;
+            return upload(&op.Wb_f, to_f(Wb));
         };
         if (upload(&H.Drb, Drb) != hipSuccess || upload(&H.Hsb, Hsb) != hipSuccess ||
-            upload(&H.Hab, Hab) != hipSuccess || make_axis(H.dph, Dph, np_, np_) != hipSuccess ||
+            upload(&H.Hab, Hab) != hipSuccess || upload(&H.Hsb_f, to_f(Hsb)) != hipSuccess ||
+            upload(&H.Hab_f, to_f(Hab)) != hipSuccess || make_axis(H.dph, Dph, np_, np_) != hipSuccess ||
             make_axis(H.ana, ana, H.K, np_) != hipSuccess || make_axis(H.syn, syn, np_, H.K) != hipSuccess ||
             upload(&H.rk, H.r_host) != hipSuccess || upload(&H.sth, sth) != hipSuccess ||
             upload(&H.cth, cth) != hipSuccess || upload(&H.sph, sph) != hipSuccess ||
             upload(&H.cph, cph) != hipSuccess || upload(&H.fmat, fm) != hipSuccess)
             return cleanup(SG_ENOMEM, "device allocation/upload of operator matrices failed");
-        if (opt->n_fields == 50) {
-            if (hipMalloc((void**)&H.H, sizeof(double) * 4 * H.npts) != hipSuccess ||
-                hipMalloc((void**)&H.dH, sizeof(double) * 12 * H.npts) != hipSuccess)
-                return cleanup(SG_ENOMEM, "gauge allocation failed");
-            (void)hipMemset(H.H, 0, sizeof(double) * 4 * H.npts);
-            (void)hipMemset(H.dH, 0, sizeof(double) * 12 * H.npts);
-        }
     }
     g->total = off;
-    g->spec_size = spec;
+    g->runs = make_runs(g, nullptr);
     size_t maxc = 0;
-    for (auto& S : g->sh) maxc = std::max(maxc, S.count);
+    spec = 0;
+    for (const Run& R : g->runs) {
+        const ShellHost& S = g->sh[R.first];
+        maxc = std::max(maxc, S.count * R.count);
+        spec = std::max(spec, size_t(R.count) * g->n_cols * S.K * S.d.n_theta * S.d.n_r);
+    }
+    g->spec_size = spec;
+    if (opt->n_fields == 50) {
+        size_t pts = 0;
+        for (auto& S : g->sh) pts += S.npts;
+        if (hipMalloc((void**)&g->Hall, sizeof(double) * 4 * pts) != hipSuccess ||
+            hipMalloc((void**)&g->dHall, sizeof(double) * 12 * pts) != hipSuccess)
+            return cleanup(SG_ENOMEM, "gauge allocation failed");
+        (void)hipMemset(g->Hall, 0, sizeof(double) * 4 * pts);
+        (void)hipMemset(g->dHall, 0, sizeof(double) * 12 * pts);
+        size_t po = 0;
+        for (auto& S : g->sh) {
+            S.H = g->Hall + 4 * po;
+            S.dH = g->dHall + 12 * po;
+            po += S.npts;
+        }
+    }
     if (hipMalloc((void**)&g->us, sizeof(double) * 2 * g->total) != hipSuccess ||
         hipMalloc((void**)&g->acc, sizeof(double) * g->total) != hipSuccess ||
         hipMalloc((void**)&g->dbuf, sizeof(double) * 3 * g->total) != hipSuccess ||
@@ -339,7 +408,7 @@ void shell_grid_destroy(sg_grid* g) {
     if (g->cap) (void)hipStreamDestroy(g->cap);
     for (auto& s : g->sh) free_shell(s);
     for (void* p : {(void*)g->us, (void*)g->acc, (void*)g->dbuf, (void*)g->tcol, (void*)g->spec, (void*)g->spec2,
-                    (void*)g->d_flag, (void*)g->d_groups})
+                    (void*)g->d_flag, (void*)g->d_groups, (void*)g->Hall, (void*)g->dHall})
         if (p) (void)hipFree(p);
     for (auto e : g->tm.ev) (void)hipEventDestroy(e);
     delete g;
@@ -402,7 +471,7 @@ sg_status swsh_filter(sg_grid* g, double* u, sg_stream_t stream) {
     if (!g || !u) return fail(SG_EINVAL, "NULL argument");
     if (g->opt.filter_kind == SG_FILTER_NONE) return SG_OK;
     hipStream_t st = (hipStream_t)stream;
-    for (int s = 0; s < (int)g->sh.size(); ++s) HIP_TRY(filter_shell(g, s, u + g->sh[s].off, st));
+    for (const Run& R : g->runs) HIP_TRY(filter_run(g, R, u + g->sh[R.first].off, st));
     return SG_OK;
 }
 
@@ -416,7 +485,7 @@ sg_status ghg_rhs(sg_grid* g, const double* u, const double* du_cart, double* rh
         const double* d = du_cart ? du_cart + 3 * S.off : g->dbuf;
         if (!du_cart) HIP_TRY(derivs_shell(g, s, u + S.off, g->dbuf, g->opt.n_fields, false, st));
         TimeScope ts(g, SG_K_RHS, st);
-        HIP_TRY(launch_rhs(v, u + S.off, d, du_cart != nullptr, rhs + S.off, nullptr, nullptr, 0.0, 0, st));
+        HIP_TRY(launch_rhs(v, 1, u + S.off, d, du_cart != nullptr, rhs + S.off, nullptr, nullptr, 0.0, 0, st));
     }
     return SG_OK;
 }
@@ -428,25 +497,37 @@ static hipError_t step_launches(sg_grid* g, double* u, const double* dt, hipStre
     double* usA = g->us;
     double* usB = g->us + g->total;
     hipError_t e;
-    for (int s = 0; s < (int)g->sh.size(); ++s) {
-        const ShellHost& S = g->sh[s];
+    for (const Run& R : make_runs(g, dt)) {
+        const ShellHost& S = g->sh[R.first];
         const KShell v = S.view(nv);
-        const double h = dt ? dt[s] : S.dt;
+        const double h = dt[R.first];
+        const int nvr = nv * R.count;                 // variables of the whole run
         double* u0 = u + S.off;
         double* a = usA + S.off;
         double* b = usB + S.off;
         double* ac = g->acc + S.off;
         const double* in[4] = {u0, a, b, a};
         double* outp[4] = {a, b, a, u0};
+        const bool mixed = g->opt.precision == SG_PREC_FP32;
+        float* dang = reinterpret_cast<float*>(g->dbuf + S.count * R.count);
         for (int stage = 1; stage <= 4; ++stage) {
-            if ((e = derivs_shell(g, s, in[stage - 1], g->dbuf, nv, false, st)) != hipSuccess) return e;
-            TimeScope ts(g, SG_K_RHS, st);
-            if ((e = launch_rhs(v, in[stage - 1], g->dbuf, false, outp[stage - 1], u0, ac, h, stage, st)) !=
-                hipSuccess)
-                return e;
+            if (mixed) {
+                if ((e = derivs_shell_mixed(g, R.first, in[stage - 1], g->dbuf, dang, nvr, st)) != hipSuccess)
+                    return e;
+                TimeScope ts(g, SG_K_RHS, st);
+                if ((e = launch_rhs_mixed(v, R.count, in[stage - 1], g->dbuf, dang, outp[stage - 1], u0, ac, h,
+                                          stage, st)) != hipSuccess)
+                    return e;
+            } else {
+                if ((e = derivs_shell(g, R.first, in[stage - 1], g->dbuf, nvr, false, st)) != hipSuccess) return e;
+                TimeScope ts(g, SG_K_RHS, st);
+                if ((e = launch_rhs(v, R.count, in[stage - 1], g->dbuf, false, outp[stage - 1], u0, ac, h, stage,
+                                    st)) != hipSuccess)
+                    return e;
+            }
         }
         if (g->opt.filter_kind != SG_FILTER_NONE)
-            if ((e = filter_shell(g, s, u0, st)) != hipSuccess) return e;
+            if ((e = filter_run(g, R, u0, st)) != hipSuccess) return e;
     }
     return hipSuccess;
 }

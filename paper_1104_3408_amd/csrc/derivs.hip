@@ -81,13 +81,14 @@ __global__ __launch_bounds__(256) void k_dr(const double* __restrict__ in, doubl
 
 // d_theta on meridian pairs.  Column c = (f * half + jp) * n_r + k; 64
 // columns per workgroup, wave w computes theta rows i = w R + r.
-template <int R>
-__global__ __launch_bounds__(256) void k_dtheta(const double* __restrict__ in, double* __restrict__ out,
-                                                const double* __restrict__ Hsb, const double* __restrict__ Hab,
+template <int R, typename T, typename O>
+__global__ __launch_bounds__(256) void k_dtheta(const double* __restrict__ in, O* __restrict__ out,
+                                                const T* __restrict__ Hsb, const T* __restrict__ Hab,
                                                 int n_r, int n_th, int n_ph, long long n_cols) {
-    extern __shared__ double sm[];   // S [n_th][64], A [n_th][64]
-    double* sS = sm;
-    double* sA = sm + n_th * 64;
+    extern __shared__ double smd[];  // S [n_th][64], A [n_th][64] in T
+    T* sm = reinterpret_cast<T*>(smd);
+    T* sS = sm;
+    T* sA = sm + n_th * 64;
     const int half = n_ph / 2;
     const long long plane = (long long)n_th * n_r;
     const long long c0 = (long long)blockIdx.x * 64;
@@ -104,21 +105,21 @@ __global__ __launch_bounds__(256) void k_dtheta(const double* __restrict__ in, d
             a = base[jp * plane];
             b = base[(jp + half) * plane];
         }
-        sS[e] = a + b;
-        sA[e] = a - b;
+        sS[e] = (T)(a + b);
+        sA[e] = (T)(a - b);
     }
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int w = wave_id();
-    const double* Sw = Hsb + (long long)w * n_th * R;
-    const double* Aw = Hab + (long long)w * n_th * R;
-    double aS[R], aA[R];
+    const T* Sw = Hsb + (long long)w * n_th * R;
+    const T* Aw = Hab + (long long)w * n_th * R;
+    T aS[R], aA[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) aS[r] = aA[r] = 0.0;
+    for (int r = 0; r < R; ++r) aS[r] = aA[r] = (T)0;
     for (int ip = 0; ip < n_th; ++ip) {
-        const double sv = sS[ip * 64 + lane], av = sA[ip * 64 + lane];
-        const double* hs = Sw + ip * R;
-        const double* ha = Aw + ip * R;
+        const T sv = sS[ip * 64 + lane], av = sA[ip * 64 + lane];
+        const T* hs = Sw + ip * R;
+        const T* ha = Aw + ip * R;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             aS[r] = fma(hs[r], sv, aS[r]);
@@ -131,13 +132,13 @@ __global__ __launch_bounds__(256) void k_dtheta(const double* __restrict__ in, d
         const int k = (int)(c - fj * n_r);
         const long long f = fj / half;
         const int jp = (int)(fj - f * half);
-        double* o = out + f * n_ph * plane + jp * plane + k;
+        O* o = out + f * n_ph * plane + jp * plane + k;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int i = w * R + r;
             if (i < n_th) {
-                o[(long long)i * n_r] = 0.5 * (aS[r] + aA[r]);
-                o[half * plane + (long long)i * n_r] = 0.5 * (aS[r] - aA[r]);
+                o[(long long)i * n_r] = (O)((T)0.5 * (aS[r] + aA[r]));
+                o[half * plane + (long long)i * n_r] = (O)((T)0.5 * (aS[r] - aA[r]));
             }
         }
     }
@@ -146,36 +147,54 @@ __global__ __launch_bounds__(256) void k_dtheta(const double* __restrict__ in, d
 // out[f][q][c] = sum_r W[q][r] (in[f][r][c] - m_c),  m_c = mean of column c
 // over r if center, else 0.  grid: (ceil(ncol/64), n_fields); in pass p wave
 // w computes rows q = (p * 4 + w) * R + r.
-template <int R>
-__global__ __launch_bounds__(256) void k_axis(const double* __restrict__ in, double* __restrict__ out,
-                                              const double* __restrict__ Wb, int n_in, int n_out, int passes,
+template <int R, typename I, typename T, typename O>
+__global__ __launch_bounds__(256) void k_axis(const I* __restrict__ in, O* __restrict__ out,
+                                              const T* __restrict__ Wb, int n_in, int n_out, int passes,
                                               long long ncol, int center) {
-    extern __shared__ double sm[];   // [n_in][64]
+    extern __shared__ double smd[];  // [n_in][64] in T
+    T* sm = reinterpret_cast<T*>(smd);
     const long long c0 = (long long)blockIdx.x * 64;
     const int nc = (int)min((long long)64, ncol - c0);
     const int f = blockIdx.y;
-    const double* src = in + (long long)f * n_in * ncol + c0;
-    for (int e = threadIdx.x; e < n_in * 64; e += 256) {
-        const int r = e >> 6, c = e & 63;
-        sm[e] = (c < nc) ? src[(long long)r * ncol + c] : 0.0;
-    }
-    __syncthreads();
+    const I* src = in + (long long)f * n_in * ncol + c0;
     const int lane = threadIdx.x & 63;
     const int w = wave_id();
+    // Column mean over the axis (center != 0), in FP64.  FP64 tiles keep the
+    // raw values and subtract per lane; FP32 tiles store (value - mean) rounded
+    // once, so the rounding is relative to the deviation from the mean.
     double m = 0.0;
-    if (center) {
-        for (int r = 0; r < n_in; ++r) m += sm[r * 64 + lane];
+    if (center && sizeof(T) == 8) {
+        if (c0 + lane < ncol)
+            for (int r = 0; r < n_in; ++r) m += (double)src[(long long)r * ncol + lane];
         m /= n_in;
     }
-    double* dst = out + (long long)f * n_out * ncol + c0;
+    double* smean = reinterpret_cast<double*>(sm + n_in * 64);   // FP32 tiles only
+    if (sizeof(T) == 4) {
+        if (threadIdx.x < 64) {
+            double t = 0.0;
+            if (center && c0 + threadIdx.x < ncol)
+                for (int r = 0; r < n_in; ++r) t += (double)src[(long long)r * ncol + threadIdx.x];
+            smean[threadIdx.x] = t / n_in;
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < n_in * 64; e += 256) {
+        const int r = e >> 6, c = e & 63;
+        T v = (T)0;
+        if (c < nc) v = (sizeof(T) == 4) ? (T)((double)src[(long long)r * ncol + c] - smean[c])
+                                         : (T)src[(long long)r * ncol + c];
+        sm[e] = v;
+    }
+    __syncthreads();
+    O* dst = out + (long long)f * n_out * ncol + c0;
     for (int p = 0; p < passes; ++p) {
-        const double* Ww = Wb + (long long)(p * 4 + w) * n_in * R;
-        double acc[R];
+        const T* Ww = Wb + (long long)(p * 4 + w) * n_in * R;
+        T acc[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) acc[r] = 0.0;
+        for (int r = 0; r < R; ++r) acc[r] = (T)0;
         for (int ri = 0; ri < n_in; ++ri) {
-            const double v = sm[ri * 64 + lane] - m;
-            const double* wr = Ww + ri * R;
+            const T v = sm[ri * 64 + lane] - (T)m;   // m = 0 for FP32 tiles
+            const T* wr = Ww + ri * R;
 #pragma unroll
             for (int r = 0; r < R; ++r) acc[r] = fma(wr[r], v, acc[r]);
         }
@@ -183,7 +202,7 @@ __global__ __launch_bounds__(256) void k_axis(const double* __restrict__ in, dou
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int q = (p * 4 + w) * R + r;
-                if (q < n_out) dst[(long long)q * ncol + lane] = acc[r];
+                if (q < n_out) dst[(long long)q * ncol + lane] = (O)acc[r];
             }
         }
     }
@@ -246,12 +265,36 @@ hipError_t launch_dr(const KShell& s, const double* in, double* out, int n_field
     return hipGetLastError();
 }
 
-hipError_t launch_dtheta(const KShell& s, const double* in, double* out, int n_fields, hipStream_t st) {
+template <typename T, typename O>
+static hipError_t dtheta_t(const KShell& s, const double* in, O* out, const T* Hsb, const T* Hab, int n_fields,
+                           hipStream_t st) {
     const long long n_cols = (long long)n_fields * (s.n_ph / 2) * s.n_r;
     const unsigned blocks = (unsigned)((n_cols + 63) / 64);
-    const size_t shm = sizeof(double) * 2 * size_t(s.n_th) * 64;
+    const size_t shm = sizeof(T) * 2 * size_t(s.n_th) * 64;
     switch (s.Hth_R) {
-#define X(R) case R: hipLaunchKernelGGL(k_dtheta<R>, dim3(blocks), dim3(256), shm, st, in, out, s.Hsb, s.Hab, s.n_r, s.n_th, s.n_ph, n_cols); break;
+#define X(R) case R: hipLaunchKernelGGL((k_dtheta<R, T, O>), dim3(blocks), dim3(256), shm, st, in, out, Hsb, Hab, s.n_r, s.n_th, s.n_ph, n_cols); break;
+        SG_R_CASES(X)
+#undef X
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_dtheta(const KShell& s, const double* in, double* out, int n_fields, hipStream_t st) {
+    return dtheta_t<double, double>(s, in, out, s.Hsb, s.Hab, n_fields, st);
+}
+
+hipError_t launch_dtheta_f32(const KShell& s, const double* in, float* out, int n_fields, hipStream_t st) {
+    return dtheta_t<float, float>(s, in, out, s.Hsb_f, s.Hab_f, n_fields, st);
+}
+
+template <typename I, typename T, typename O>
+static hipError_t axis_t(const AxisOp& op, const T* Wb, const I* in, O* out, long long ncol, int n_fields,
+                         int center, hipStream_t st) {
+    const unsigned bx = (unsigned)((ncol + 63) / 64);
+    const size_t shm = sizeof(T) * size_t(op.n_in) * 64 + (sizeof(T) == 4 ? 64 * sizeof(double) : 0);
+    switch (op.R) {
+#define X(R) case R: hipLaunchKernelGGL((k_axis<R, I, T, O>), dim3(bx, n_fields), dim3(256), shm, st, in, out, Wb, op.n_in, op.n_out, op.passes, ncol, center); break;
         SG_R_CASES(X)
 #undef X
         default: return hipErrorInvalidValue;
@@ -261,15 +304,22 @@ hipError_t launch_dtheta(const KShell& s, const double* in, double* out, int n_f
 
 hipError_t launch_axis(const AxisOp& op, const double* in, double* out, long long ncol, int n_fields, int center,
                        hipStream_t st) {
-    const unsigned bx = (unsigned)((ncol + 63) / 64);
-    const size_t shm = sizeof(double) * size_t(op.n_in) * 64;
-    switch (op.R) {
-#define X(R) case R: hipLaunchKernelGGL(k_axis<R>, dim3(bx, n_fields), dim3(256), shm, st, in, out, op.Wb, op.n_in, op.n_out, op.passes, ncol, center); break;
-        SG_R_CASES(X)
-#undef X
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    return axis_t<double, double, double>(op, op.Wb, in, out, ncol, n_fields, center, st);
+}
+
+hipError_t launch_axis_f32(const AxisOp& op, const double* in, float* out, long long ncol, int n_fields, int center,
+                           hipStream_t st) {
+    return axis_t<double, float, float>(op, op.Wb_f, in, out, ncol, n_fields, center, st);
+}
+
+hipError_t launch_axis_ff(const AxisOp& op, const float* in, float* out, long long ncol, int n_fields,
+                          hipStream_t st) {
+    return axis_t<float, float, float>(op, op.Wb_f, in, out, ncol, n_fields, 0, st);
+}
+
+hipError_t launch_axis_fd(const AxisOp& op, const float* in, double* out, long long ncol, int n_fields,
+                          hipStream_t st) {
+    return axis_t<float, float, double>(op, op.Wb_f, in, out, ncol, n_fields, 0, st);
 }
 
 hipError_t launch_chain(const KShell& s, double* du, int n_fields, hipStream_t st) {

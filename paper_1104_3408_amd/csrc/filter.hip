@@ -124,6 +124,8 @@ __device__ __forceinline__ Cx10 sym2_to_cx10(const Sym2& c) {
 
 __global__ __launch_bounds__(256) void k_decompose(KShell s, const double* __restrict__ u, double* __restrict__ t) {
     const long long np = s.npts;
+    u += (long long)blockIdx.y * s.n_v * np;   // shell of a run
+    t += (long long)blockIdx.y * s.n_v * np;
     const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np) return;
     const int i = (int)((p / s.n_r) % s.n_th);
@@ -189,6 +191,8 @@ __global__ __launch_bounds__(256) void k_decompose(KShell s, const double* __res
 
 __global__ __launch_bounds__(256) void k_recompose(KShell s, const double* __restrict__ t, double* __restrict__ u) {
     const long long np = s.npts;
+    u += (long long)blockIdx.y * s.n_v * np;   // shell of a run
+    t += (long long)blockIdx.y * s.n_v * np;
     const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np) return;
     const int i = (int)((p / s.n_r) % s.n_th);
@@ -233,12 +237,17 @@ __global__ __launch_bounds__(256) void k_recompose(KShell s, const double* __res
 
 // spec[c][q][i][k] -> spec2, q = 0 (a_0), 2m-1 (a_m), 2m (b_m).
 // Thread per (group, m, i, k), k fastest.
-__global__ __launch_bounds__(256) void k_ftheta(int n_r, int n_th, int m_keep, int n_groups,
+__global__ __launch_bounds__(256) void k_ftheta(int n_r, int n_th, int m_keep, int n_groups, int n_cols,
                                                 const double* __restrict__ spec, double* __restrict__ spec2,
                                                 const double* __restrict__ fmat,
                                                 const FiltGroup* __restrict__ groups) {
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long per_m = (long long)n_th * n_r;
+    {   // shell of a run
+        const long long so = (long long)blockIdx.y * n_cols * (2 * m_keep + 1) * per_m;
+        spec += so;
+        spec2 += so;
+    }
     const long long total = per_m * (m_keep + 1) * n_groups;
     if (e >= total) return;
     const int k = (int)(e % n_r);
@@ -298,23 +307,23 @@ __global__ __launch_bounds__(256) void k_ftheta(int n_r, int n_th, int m_keep, i
 
 }  // namespace
 
-hipError_t launch_decompose(const KShell& s, const double* u, double* t, hipStream_t st) {
-    const unsigned blocks = (unsigned)((s.npts + 255) / 256);
-    hipLaunchKernelGGL(k_decompose, dim3(blocks), dim3(256), 0, st, s, u, t);
+hipError_t launch_decompose(const KShell& s, int count, const double* u, double* t, hipStream_t st) {
+    const dim3 grid((unsigned)((s.npts + 255) / 256), (unsigned)count);
+    hipLaunchKernelGGL(k_decompose, grid, dim3(256), 0, st, s, u, t);
     return hipGetLastError();
 }
 
-hipError_t launch_recompose(const KShell& s, const double* t, double* u, hipStream_t st) {
-    const unsigned blocks = (unsigned)((s.npts + 255) / 256);
-    hipLaunchKernelGGL(k_recompose, dim3(blocks), dim3(256), 0, st, s, t, u);
+hipError_t launch_recompose(const KShell& s, int count, const double* t, double* u, hipStream_t st) {
+    const dim3 grid((unsigned)((s.npts + 255) / 256), (unsigned)count);
+    hipLaunchKernelGGL(k_recompose, grid, dim3(256), 0, st, s, t, u);
     return hipGetLastError();
 }
 
-hipError_t launch_ftheta(const KShell& s, const double* spec, double* spec2, const double* fmat,
-                         const FiltGroup* groups, int n_groups, int m_keep, hipStream_t st) {
+hipError_t launch_ftheta(const KShell& s, int count, const double* spec, double* spec2, const double* fmat,
+                         const FiltGroup* groups, int n_groups, int n_cols, int m_keep, hipStream_t st) {
     const long long total = (long long)s.n_th * s.n_r * (m_keep + 1) * n_groups;
-    const unsigned blocks = (unsigned)((total + 255) / 256);
-    hipLaunchKernelGGL(k_ftheta, dim3(blocks), dim3(256), 0, st, s.n_r, s.n_th, m_keep, n_groups, spec, spec2,
+    const dim3 grid((unsigned)((total + 255) / 256), (unsigned)count);
+    hipLaunchKernelGGL(k_ftheta, grid, dim3(256), 0, st, s.n_r, s.n_th, m_keep, n_groups, n_cols, spec, spec2,
                        fmat, groups);
     return hipGetLastError();
 }

@@ -18,6 +18,8 @@ struct KShell {
     const double* Hsb;        // H_L + H_R of the folded theta matrix, wave-blocked
     const double* Hab;        // H_L - H_R, wave-blocked
     int Dr_R, Hth_R;          // rows per wave of the blocked d_r / d_theta operators
+    const float* Hsb_f;       // FP32 copies for the mixed-precision path
+    const float* Hab_f;
     const double* rk;         // radii
     const double* sth; const double* cth;   // sin, cos theta_i
     const double* sph; const double* cph;   // sin, cos phi_j
@@ -34,6 +36,7 @@ struct FiltGroup {
 // A matrix applied along the phi axis (n_out x n_in), wave-blocked.
 struct AxisOp {
     double* Wb = nullptr;
+    float* Wb_f = nullptr;          // FP32 copy for the mixed-precision path
     int n_in = 0, n_out = 0, R = 0, passes = 0;
 };
 
@@ -46,6 +49,7 @@ struct ShellHost {
     double dt = 0;
     int m_keep = 0, K = 0;
     double *Drb = nullptr, *Hsb = nullptr, *Hab = nullptr;
+    float *Hsb_f = nullptr, *Hab_f = nullptr;
     int Dr_R = 0, Hth_R = 0;
     AxisOp dph, ana, syn;                    // d_phi, Fourier analysis, Fourier synthesis
     double *rk = nullptr, *sth = nullptr, *cth = nullptr, *sph = nullptr, *cph = nullptr;
@@ -56,6 +60,11 @@ struct ShellHost {
 };
 
 // One captured filtered RK4 step (all shells), replayed per step.
+// Consecutive shells with identical grids: one launch per kernel covers them.
+struct Run {
+    int first = 0, count = 0;
+};
+
 struct StepGraph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -76,6 +85,8 @@ struct Timing {
 struct sg_grid {
     sg_options opt{};
     std::vector<sg::ShellHost> sh;
+    std::vector<sg::Run> runs;
+    double *Hall = nullptr, *dHall = nullptr;   // static gauge of all shells (4, 12 fields per point)
     size_t total = 0;                 // state size in doubles
     int n_sets = 0;
     std::vector<sg::FiltGroup> groups;
@@ -95,17 +106,27 @@ namespace sg {
 // Launchers (stream-ordered; return a HIP error code).
 hipError_t launch_dr(const KShell& s, const double* in, double* out, int n_fields, hipStream_t st);
 hipError_t launch_dtheta(const KShell& s, const double* in, double* out, int n_fields, hipStream_t st);
+hipError_t launch_dtheta_f32(const KShell& s, const double* in, float* out, int n_fields, hipStream_t st);
+hipError_t launch_axis_f32(const AxisOp& op, const double* in, float* out, long long ncol, int n_fields, int center,
+                           hipStream_t st);
+hipError_t launch_axis_ff(const AxisOp& op, const float* in, float* out, long long ncol, int n_fields, hipStream_t st);
+hipError_t launch_axis_fd(const AxisOp& op, const float* in, double* out, long long ncol, int n_fields,
+                          hipStream_t st);
 hipError_t launch_axis(const AxisOp& op, const double* in, double* out, long long ncol, int n_fields, int center,
                        hipStream_t st);
 std::vector<double> block_operator(const std::vector<double>& W, int n_out, int n_in, int R, int passes);
 void blocked_shape(int n_out, int& R, int& passes);
 hipError_t launch_chain(const KShell& s, double* du, int n_fields, hipStream_t st);
-hipError_t launch_rhs(const KShell& s, const double* u, const double* du, bool cart, double* out,
+// Kernels taking `count` process a run of `count` identical shells stored one
+// after the other (shell index in blockIdx.y).
+hipError_t launch_rhs(const KShell& s, int count, const double* u, const double* du, bool cart, double* out,
                       const double* ubase, double* acc, double dt, int stage, hipStream_t st);
-hipError_t launch_decompose(const KShell& s, const double* u, double* t, hipStream_t st);
-hipError_t launch_recompose(const KShell& s, const double* t, double* u, hipStream_t st);
-hipError_t launch_ftheta(const KShell& s, const double* spec, double* spec2, const double* fmat,
-                         const FiltGroup* groups, int n_groups, int m_keep, hipStream_t st);
+hipError_t launch_rhs_mixed(const KShell& s, int count, const double* u, const double* dr, const float* dang,
+                            double* out, const double* ubase, double* acc, double dt, int stage, hipStream_t st);
+hipError_t launch_decompose(const KShell& s, int count, const double* u, double* t, hipStream_t st);
+hipError_t launch_recompose(const KShell& s, int count, const double* t, double* u, hipStream_t st);
+hipError_t launch_ftheta(const KShell& s, int count, const double* spec, double* spec2, const double* fmat,
+                         const FiltGroup* groups, int n_groups, int n_cols, int m_keep, hipStream_t st);
 hipError_t launch_initial(const KShell& s, const double* g10, const double* dg, double* u,
                           double* H, hipStream_t st);
 hipError_t launch_finite_check(const double* u, size_t n, int* flag, hipStream_t st);

@@ -33,11 +33,24 @@ constexpr int kWaves = 5;     // wave w owns symmetric pairs 2w and 2w+1
 // everything that belongs to its two symmetric pairs ab: the sources and
 // derivative terms of d_t g_ab, d_t Pi_ab and d_t Phi_xab, the boundary
 // operator (which couples only fields of one pair) and the RK4 stage update.
-template <int NV>
+template <int NV, typename TD>
 __global__ __launch_bounds__(320) void k_rhs(KShell s, const double* __restrict__ u,
-                                             const double* __restrict__ du, int cart,
+                                             const double* __restrict__ du, const TD* __restrict__ dang, int cart,
                                              double* __restrict__ out, const double* __restrict__ ubase,
-                                             double* __restrict__ acc, double dt, int stage) {
+                                             double* __restrict__ acc, double dt, int stage, long long blk) {
+    // blockIdx.y: shell of a run of identical shells stored one after the
+    // other; blk: stride between the derivative blocks (d_r, d_theta, d_phi).
+    {
+        const long long so = (long long)blockIdx.y * NV * s.npts;
+        u += so;
+        du += so;
+        dang += so;
+        out += so;
+        if (ubase) ubase += so;
+        if (acc) acc += so;
+        s.H += (long long)blockIdx.y * 4 * s.npts;
+        s.dH += (long long)blockIdx.y * 12 * s.npts;
+    }
     __shared__ double su[NV][kPts];          // state of the 64 points
     __shared__ double sH[4][kPts];           // H_a
     __shared__ double sdH[4][4][kPts];       // d_a H_b (a = t from the state or 0)
@@ -53,7 +66,6 @@ __global__ __launch_bounds__(320) void k_rhs(KShell s, const double* __restrict_
     const long long p0 = (long long)blockIdx.x * kPts;
     const long long p = p0 + lane;
     const bool ok = p < np;
-    const long long blk = (long long)NV * np;
 
     // ---- stage variables; points past the end get Minkowski data -----------
     for (int e = threadIdx.x; e < NV * kPts; e += kWaves * 64) {
@@ -115,7 +127,8 @@ __global__ __launch_bounds__(320) void k_rhs(KShell s, const double* __restrict_
     // that it is not live across the algebra.
     auto cartd = [&](int mu, double d[3]) {
         const long long q = (long long)mu * np + p;
-        const double d0 = du[q], d1 = du[blk + q], d2 = du[2 * blk + q];
+        // d_r in FP64; d_theta, d_phi in TD (FP32 on the mixed-precision path)
+        const double d0 = du[q], d1 = (double)dang[q], d2 = (double)dang[blk + q];
         if (cart) {
             d[0] = d0; d[1] = d1; d[2] = d2;
         } else {
@@ -417,15 +430,30 @@ __global__ __launch_bounds__(256) void k_finite(const double* __restrict__ u, si
 
 }  // namespace
 
-hipError_t launch_rhs(const KShell& s, const double* u, const double* du, bool cart, double* out,
+hipError_t launch_rhs(const KShell& s, int count, const double* u, const double* du, bool cart, double* out,
                       const double* ubase, double* acc, double dt, int stage, hipStream_t st) {
-    const unsigned blocks = (unsigned)((s.npts + kPts - 1) / kPts);
+    const dim3 grid((unsigned)((s.npts + kPts - 1) / kPts), (unsigned)count);
+    const long long blk = (long long)count * s.n_v * s.npts;
+    const double* dang = du + blk;
     if (s.n_v == 58)
-        hipLaunchKernelGGL(k_rhs<58>, dim3(blocks), dim3(kWaves * 64), 0, st, s, u, du, cart ? 1 : 0, out, ubase, acc,
-                           dt, stage);
+        hipLaunchKernelGGL((k_rhs<58, double>), grid, dim3(kWaves * 64), 0, st, s, u, du, dang, cart ? 1 : 0,
+                           out, ubase, acc, dt, stage, blk);
     else
-        hipLaunchKernelGGL(k_rhs<50>, dim3(blocks), dim3(kWaves * 64), 0, st, s, u, du, cart ? 1 : 0, out, ubase, acc,
-                           dt, stage);
+        hipLaunchKernelGGL((k_rhs<50, double>), grid, dim3(kWaves * 64), 0, st, s, u, du, dang, cart ? 1 : 0,
+                           out, ubase, acc, dt, stage, blk);
+    return hipGetLastError();
+}
+
+hipError_t launch_rhs_mixed(const KShell& s, int count, const double* u, const double* dr, const float* dang,
+                            double* out, const double* ubase, double* acc, double dt, int stage, hipStream_t st) {
+    const dim3 grid((unsigned)((s.npts + kPts - 1) / kPts), (unsigned)count);
+    const long long blk = (long long)count * s.n_v * s.npts;
+    if (s.n_v == 58)
+        hipLaunchKernelGGL((k_rhs<58, float>), grid, dim3(kWaves * 64), 0, st, s, u, dr, dang, 0, out, ubase,
+                           acc, dt, stage, blk);
+    else
+        hipLaunchKernelGGL((k_rhs<50, float>), grid, dim3(kWaves * 64), 0, st, s, u, dr, dang, 0, out, ubase,
+                           acc, dt, stage, blk);
     return hipGetLastError();
 }
 
