@@ -48,6 +48,48 @@ def algorithmic_bytes(cls, n_r, n_th, n_ph, n_v, K):
     return per_fp * fp + extra
 
 
+def batch_workload(name):
+    """Shell lists of the batched workloads (grouped by size class so that
+    identical shells are adjacent)."""
+    if name == "batch64":
+        sizes = [(17, 16), (25, 24), (33, 32), (49, 48)]
+        return [(a, b, 2 * b, 1.8, 11.8) for (a, b) in sizes for _ in range(16)], 50
+    if name == "large8":
+        return [(65, 64, 128, 1.8, 21.8)] * 8, 58
+    raise ValueError(name)
+
+
+def run_variant(shells, n_v, precision, steps, warmup, seed0):
+    """Throughput of one workload: seeded perturbed Kerr-Schild data on every
+    shell (seed0 + shell index), filtered RK4 steps with the step graph."""
+    import numpy as np
+    import torch
+    from paper_1104_3408_amd import shellspec as ss
+    from paper_1104_3408_amd import inputs
+    g = ss.ShellGrid(shells, n_fields=n_v, filter="Yn", n_f=4, courant=4.0, precision=precision)
+    g10, extra = [], []
+    for k in range(len(shells)):
+        r, th, ph = g.coords(k)
+        g10.append(inputs.perturbed_kerr_schild(seed0 + k, r, th, ph).ravel())
+        if n_v == 58:
+            dH, Q = inputs.gauge_perturbation(seed0 + 1000 + k, r, th, ph)
+            extra.append(np.concatenate([dH, Q]).ravel())
+    u = torch.zeros(g.state_size, dtype=torch.float64, device="cuda")
+    ex = torch.from_numpy(np.concatenate(extra)).cuda() if extra else None
+    g.kerr_schild_data(torch.from_numpy(np.concatenate(g10)).cuda(), u, extra8=ex)
+    del g10, extra, ex
+    g.rk_step(u, warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.rk_step(u, steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    fp = sum(n_v * a * b * c for (a, b, c, _, _) in shells)
+    res = {"field_points": fp, "ms_per_step": 1e3 * (t1 - t0) / steps, "value": fp * steps / (t1 - t0),
+           "steps": steps, "state_finite": bool(torch.isfinite(u).all().item())}
+    return res, u, g
+
+
 def cpu_baseline(shell, g10, dt, gpu_state_after_one_step):
     """Oracle (numpy FP64) on one filtered RK4 step of the same workload."""
     import numpy as np
@@ -86,6 +128,9 @@ def main():
     ap.add_argument("--workload", default="ks33", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="skip the per-kernel HIP events")
+    ap.add_argument("--no-variants", action="store_true", help="skip the mixed-precision and batched workloads")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="run one device copy of this many MiB (a known-size kernel for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: shells are independent and this build has no multi-GPU path "
@@ -159,6 +204,39 @@ def main():
         out["timing_pass_ms_per_step"] = 1e3 * (t3 - t2) / args.steps
         tot = sum(k["total_ms"] for k in kern.values())
         out["kernel_time_share"] = {c: kern[c]["total_ms"] / tot for c in kern}
+    if args.copy_probe_mb:
+        src = torch.empty(args.copy_probe_mb * (1 << 20) // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes_each_way"] = src.numel() * 8
+        del src, dst
+    if not args.no_variants:
+        var = {}
+        # same shell, angular derivatives in FP32; error vs the FP64 GPU state
+        # (which matches the oracle to 1e-12) after the same number of steps
+        res, um, gm = run_variant(shells, n_v, ss.SG_PREC_FP32, args.steps, args.warmup, 2)
+        uref, _, gr = None, None, None
+        res64, uref, gr = run_variant(shells, n_v, ss.SG_PREC_FP64, args.steps, args.warmup, 2)
+        d = (um - uref).abs().max().item() / uref.abs().max().item()
+        res["max_rel_diff_vs_fp64_gpu"] = d
+        res["speedup_vs_fp64"] = res["value"] / res64["value"]
+        var["mixed_fp32_angular"] = res
+        del um, uref, gm, gr
+        for name, steps in (("batch64", 20), ("large8", 10)):
+            bshells, bnv = batch_workload(name)
+            r64, u64, g64 = run_variant(bshells, bnv, ss.SG_PREC_FP64, steps, 2, 4000 if name == "batch64" else 5000)
+            u64h = u64.clone()
+            del u64, g64
+            torch.cuda.empty_cache()
+            r32, u32, g32 = run_variant(bshells, bnv, ss.SG_PREC_FP32, steps, 2, 4000 if name == "batch64" else 5000)
+            r32["max_rel_diff_vs_fp64_gpu"] = (u32 - u64h).abs().max().item() / u64h.abs().max().item()
+            r32["speedup_vs_fp64"] = r32["value"] / r64["value"]
+            var[name] = {"shells": len(bshells), "n_fields": bnv, "fp64": r64, "mixed_fp32_angular": r32}
+            del u32, g32, u64h
+            torch.cuda.empty_cache()
+        out["variants"] = var
     if not args.no_cpu_baseline and len(shells) == 1:
         base, err = cpu_baseline(shells[0], g10.reshape((10,) + (shells[0][2], shells[0][1], shells[0][0])),
                                  g.info(0)[2], u1_host)

@@ -70,6 +70,19 @@ void build_groups(sg_grid* g) {
         const bool graded = g->opt.filter_kind == SG_FILTER_YG;
         for (int mu = 0; mu < nv; ++mu) G.push_back({mu, -1, graded ? spatial_degree(mu) : 0, 1});
     }
+    // column sets of the theta filter: one per (matrix set, real/complex)
+    std::stable_sort(G.begin(), G.end(), [](const FiltGroup& a, const FiltGroup& b) {
+        return a.set != b.set ? a.set < b.set : (a.im >= 0) < (b.im >= 0);
+    });
+    g->fsets.clear();
+    g->max_groups = 0;
+    for (size_t i = 0; i < G.size();) {
+        size_t j = i;
+        while (j < G.size() && G[j].set == G[i].set && (G[j].im >= 0) == (G[i].im >= 0)) ++j;
+        g->fsets.push_back({int(i), int(j - i), G[i].set, G[i].im >= 0 ? 1 : 0});
+        g->max_groups = std::max(g->max_groups, int(j - i));
+        i = j;
+    }
 }
 
 // n_f of filter matrix set s: Yn sets are spins |n| = s with the global n_f;
@@ -96,7 +109,7 @@ sg_status check_opts(const sg_shell_desc* shells, int n_shells, const sg_options
 }
 
 void free_shell(ShellHost& s) {
-    for (double* p : {s.Drb, s.Hsb, s.Hab, s.dph.Wb, s.ana.Wb, s.syn.Wb, s.rk, s.sth, s.cth, s.sph, s.cph, s.fmat})
+    for (double* p : {s.Drb, s.Hsb, s.Hab, s.dph.Wb, s.ana.Wb, s.syn.Wb, s.rk, s.sth, s.cth, s.sph, s.cph, s.Fb})
         if (p) (void)hipFree(p);
     for (float* p : {s.Hsb_f, s.Hab_f, s.dph.Wb_f, s.ana.Wb_f, s.syn.Wb_f})
         if (p) (void)hipFree(p);
@@ -196,8 +209,8 @@ hipError_t filter_run(sg_grid* g, const Run& R, double* u, hipStream_t st) {
     }
     {
         TimeScope ts(g, SG_K_FTHETA, st);
-        if ((e = launch_ftheta(v, R.count, g->spec, g->spec2, S.fmat, g->d_groups, (int)g->groups.size(), g->n_cols,
-                               S.m_keep, st)) != hipSuccess)
+        const FiltPlan fp{S.Fb, g->d_groups, g->d_fsets, (int)g->fsets.size(), g->max_groups, S.F_R};
+        if ((e = launch_ftheta(v, R.count, g->spec, g->spec2, fp, g->n_cols, S.m_keep, st)) != hipSuccess)
             return e;
     }
     {
@@ -308,18 +321,21 @@ sg_status shell_grid_create(const sg_shell_desc* shells, int n_shells, const sg_
             for (int b = 0; b < np_; ++b) Dph[size_t(a) * np_ + b] = fd[((a - b) % np_ + np_) % np_];
         std::vector<double> ana, syn;
         fourier_real_matrices(np_, H.m_keep, ana, syn);
-        const size_t NN = size_t(nt) * nt;
-        std::vector<double> fm(size_t(g->n_sets) * (H.m_keep + 1) * 2 * NN, 0.0);
+        // theta filters F^{|n|}_m, rows blocked over the 4 waves of k_ftheta
+        H.F_R = (nt + 3) / 4;
+        const size_t per_mat = size_t(4) * nt * H.F_R;
+        std::vector<double> fm(size_t(g->n_sets) * (H.m_keep + 1) * per_mat, 0.0);
         for (int k = 0; k < g->n_sets; ++k) {
             const int n = set_spin(g, k), nf = set_nf(g, k);
             for (int m = 0; m <= H.m_keep; ++m) {
-                std::vector<double> Fp = filter_matrix(n, m, nt, nf);
-                std::vector<double> Fm = (n == 0) ? Fp : filter_matrix(-n, m, nt, nf);
-                double* Sd = fm.data() + ((size_t(k) * (H.m_keep + 1) + m) * 2) * NN;
-                for (size_t e = 0; e < NN; ++e) {
-                    Sd[e] = 0.5 * (Fp[e] + Fm[e]);
-                    Sd[NN + e] = 0.5 * (Fp[e] - Fm[e]);
-                }
+                const std::vector<double> F = filter_matrix(n, m, nt, nf);
+                double* Fb = fm.data() + (size_t(k) * (H.m_keep + 1) + m) * per_mat;
+                for (int w = 0; w < 4; ++w)
+                    for (int ip = 0; ip < nt; ++ip)
+                        for (int r = 0; r < H.F_R; ++r) {
+                            const int i = w * H.F_R + r;
+                            Fb[(size_t(w) * nt + ip) * H.F_R + r] = i < nt ? F[size_t(i) * nt + ip] : 0.0;
+                        }
             }
         }
         std::vector<double> Hth = theta_half_matrix(nt), Hs(size_t(nt) * nt), Ha(size_t(nt) * nt);
@@ -350,7 +366,7 @@ sg_status shell_grid_create(const sg_shell_desc* shells, int n_shells, const sg_
             make_axis(H.ana, ana, H.K, np_) != hipSuccess || make_axis(H.syn, syn, np_, H.K) != hipSuccess ||
             upload(&H.rk, H.r_host) != hipSuccess || upload(&H.sth, sth) != hipSuccess ||
             upload(&H.cth, cth) != hipSuccess || upload(&H.sph, sph) != hipSuccess ||
-            upload(&H.cph, cph) != hipSuccess || upload(&H.fmat, fm) != hipSuccess)
+            upload(&H.cph, cph) != hipSuccess || upload(&H.Fb, fm) != hipSuccess)
             return cleanup(SG_ENOMEM, "device allocation/upload of operator matrices failed");
     }
     g->total = off;
@@ -386,7 +402,8 @@ sg_status shell_grid_create(const sg_shell_desc* shells, int n_shells, const sg_
         hipMalloc((void**)&g->spec2, sizeof(double) * spec) != hipSuccess ||
         hipMalloc((void**)&g->d_flag, sizeof(int)) != hipSuccess)
         return cleanup(SG_ENOMEM, "workspace allocation failed");
-    if (upload(&g->d_groups, g->groups) != hipSuccess) return cleanup(SG_ENOMEM, "group upload failed");
+    if (upload(&g->d_groups, g->groups) != hipSuccess || upload(&g->d_fsets, g->fsets) != hipSuccess)
+        return cleanup(SG_ENOMEM, "group upload failed");
     if (hipMemset(g->spec2, 0, sizeof(double) * spec) != hipSuccess) return cleanup(SG_EHIP, "memset failed");
     if (gauge_H) {
         sg_status s2 = sg_set_gauge(g, gauge_H, nullptr);
@@ -408,7 +425,7 @@ void shell_grid_destroy(sg_grid* g) {
     if (g->cap) (void)hipStreamDestroy(g->cap);
     for (auto& s : g->sh) free_shell(s);
     for (void* p : {(void*)g->us, (void*)g->acc, (void*)g->dbuf, (void*)g->tcol, (void*)g->spec, (void*)g->spec2,
-                    (void*)g->d_flag, (void*)g->d_groups, (void*)g->Hall, (void*)g->dHall})
+                    (void*)g->d_flag, (void*)g->d_groups, (void*)g->d_fsets, (void*)g->Hall, (void*)g->dHall})
         if (p) (void)hipFree(p);
     for (auto e : g->tm.ev) (void)hipEventDestroy(e);
     delete g;

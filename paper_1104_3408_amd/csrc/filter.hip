@@ -235,74 +235,127 @@ __global__ __launch_bounds__(256) void k_recompose(KShell s, const double* __res
     }
 }
 
-// spec[c][q][i][k] -> spec2, q = 0 (a_0), 2m-1 (a_m), 2m (b_m).
-// Thread per (group, m, i, k), k fastest.
-__global__ __launch_bounds__(256) void k_ftheta(int n_r, int n_th, int m_keep, int n_groups, int n_cols,
+// theta filter, spec[c][q][i][k] -> spec2 (q = 0: a_0; 2m-1: a_m; 2m: b_m).
+// Workgroup (column tile, m, column set, shell of the run): the columns of a
+// set are (group, r_k) pairs, one per lane, all real or all complex and all
+// filtered with the same F = F^{|n|}_m; wave w forms theta rows w R + r, with
+// the rows of F wave-uniform (scalar operands, wave-blocked copy Fb).
+//
+// With F_+ = F^n_m and F_- = F^{-n}_m = J F^{|n|}_m J (J reverses theta; the
+// staggered theta grid is symmetric about the equator), the S/D form of the
+// file header is, for a complex group at m > 0,
+//   P1 = F_+ (a^x + b^y), M1 = F_- (a^x - b^y):  a^x' = (P1 + M1)/2, b^y' = (P1 - M1)/2
+//   P2 = F_- (a^y + b^x), M2 = F_+ (a^y - b^x):  a^y' = (P2 + M2)/2, b^x' = (P2 - M2)/2,
+// two passes of two vectors and half the products of S and D.  Real groups
+// filter a and b with F; at m = 0 a complex group filters a^x and a^y with F
+// (F^n_0 = F^{-n}_0).  J F J v is F applied to v reversed, read back reversed.
+template <int R>
+__global__ __launch_bounds__(256) void k_ftheta(int n_r, int n_th, int m_keep, int n_cols_state,
                                                 const double* __restrict__ spec, double* __restrict__ spec2,
-                                                const double* __restrict__ fmat,
-                                                const FiltGroup* __restrict__ groups) {
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+                                                const double* __restrict__ Fb, const FiltGroup* __restrict__ groups,
+                                                const FiltSet* __restrict__ sets, int n_sets) {
+    extern __shared__ double sm[];   // v0, v1: [n_th][64]
+    const int m = blockIdx.y;
+    const FiltSet fs = sets[blockIdx.z % n_sets];
+    const int shell = blockIdx.z / n_sets;
     const long long per_m = (long long)n_th * n_r;
-    {   // shell of a run
-        const long long so = (long long)blockIdx.y * n_cols * (2 * m_keep + 1) * per_m;
+    const long long col = (long long)(2 * m_keep + 1) * per_m;   // one storage column
+    {
+        const long long so = (long long)shell * n_cols_state * col;
         spec += so;
         spec2 += so;
     }
-    const long long total = per_m * (m_keep + 1) * n_groups;
-    if (e >= total) return;
-    const int k = (int)(e % n_r);
-    const int i = (int)((e / n_r) % n_th);
-    const int m = (int)((e / per_m) % (m_keep + 1));
-    const int gi = (int)(e / (per_m * (m_keep + 1)));
-    const FiltGroup G = groups[gi];
-    const int K = 2 * m_keep + 1;
-    const long long NN = (long long)n_th * n_th;
-    const double* S = fmat + ((long long)(G.set * (m_keep + 1) + m) * 2) * NN + (long long)i * n_th;
-    const double* D = S + NN;
-    const long long col = (long long)K * per_m;   // one storage column
+    const long long c0 = (long long)blockIdx.x * 64;
+    if (c0 >= (long long)fs.count * n_r) return;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const long long c = c0 + lane;
+    const bool ok = c < (long long)fs.count * n_r;
+    const int gi = ok ? (int)(c / n_r) : 0;
+    const int k = ok ? (int)(c - (long long)gi * n_r) : 0;
+    const FiltGroup G = groups[fs.first + gi];
     const int qa = (m == 0) ? 0 : 2 * m - 1, qb = 2 * m;
-    const double* ax = spec + G.re * col + qa * per_m + k;
-    const double* bx = spec + G.re * col + qb * per_m + k;
-    double* oax = spec2 + G.re * col + qa * per_m + i * (long long)n_r + k;
-    double* obx = spec2 + G.re * col + qb * per_m + i * (long long)n_r + k;
-    if (G.im < 0) {
-        double sa = 0.0, sb = 0.0;
-        for (int ip = 0; ip < n_th; ++ip) {
-            sa = fma(S[ip], ax[ip * n_r], sa);
-            if (m > 0) sb = fma(S[ip], bx[ip * n_r], sb);
+    const double* Fw = Fb + ((long long)(fs.mat * (m_keep + 1) + m) * 4 + w) * n_th * R;
+    double* v0 = sm;
+    double* v1 = sm + n_th * 64;
+    const bool mix = fs.cplx && m > 0;   // block-uniform
+    const bool neg = G.sign < 0;          // F_+ = J F J for a negative spin
+    for (int pass = 0; pass < (mix ? 2 : 1); ++pass) {
+        const double* x0;
+        const double* x1 = nullptr;
+        bool rev0 = false, rev1 = false;
+        if (!fs.cplx) {
+            x0 = spec + G.re * col + qa * per_m + k;
+            if (m > 0) x1 = spec + G.re * col + qb * per_m + k;
+        } else if (m == 0) {
+            x0 = spec + G.re * col + k;
+            x1 = spec + G.im * col + k;
+        } else if (pass == 0) {   // a^x, b^y -> P1 (F_+), M1 (F_-)
+            x0 = spec + G.re * col + qa * per_m + k;
+            x1 = spec + G.im * col + qb * per_m + k;
+            rev0 = neg;
+            rev1 = !neg;
+        } else {                  // a^y, b^x -> P2 (F_-), M2 (F_+)
+            x0 = spec + G.im * col + qa * per_m + k;
+            x1 = spec + G.re * col + qb * per_m + k;
+            rev0 = !neg;
+            rev1 = neg;
         }
-        *oax = sa;
-        if (m > 0) *obx = sb;
-        return;
-    }
-    const double* ay = spec + G.im * col + qa * per_m + k;
-    const double* by = spec + G.im * col + qb * per_m + k;
-    double* oay = spec2 + G.im * col + qa * per_m + i * (long long)n_r + k;
-    double* oby = spec2 + G.im * col + qb * per_m + i * (long long)n_r + k;
-    const double sg = (double)G.sign;
-    if (m == 0) {
-        double sx = 0.0, sy = 0.0;
-        for (int ip = 0; ip < n_th; ++ip) {
-            sx = fma(S[ip], ax[ip * n_r], sx);
-            sy = fma(S[ip], ay[ip * n_r], sy);
+        if (pass > 0) __syncthreads();
+        for (int ip = w; ip < n_th; ip += 4) {
+            double a = 0.0, b = 0.0;
+            if (ok) {
+                const double va = x0[ip * (long long)n_r];
+                const double vb = x1 ? x1[ip * (long long)n_r] : 0.0;
+                a = mix ? va + vb : va;
+                b = mix ? va - vb : vb;
+            }
+            v0[(rev0 ? n_th - 1 - ip : ip) * 64 + lane] = a;
+            v1[(rev1 ? n_th - 1 - ip : ip) * 64 + lane] = b;
         }
-        *oax = sx;
-        *oay = sy;
-        return;
+        __syncthreads();
+        double acc0[R], acc1[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc0[r] = acc1[r] = 0.0;
+        for (int ip = 0; ip < n_th; ++ip) {
+            const double a = v0[ip * 64 + lane], b = v1[ip * 64 + lane];
+            const double* f = Fw + ip * R;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                acc0[r] = fma(f[r], a, acc0[r]);
+                acc1[r] = fma(f[r], b, acc1[r]);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = w * R + r;
+            if (i < n_th) {
+                v0[i * 64 + lane] = acc0[r];
+                v1[i * 64 + lane] = acc1[r];
+            }
+        }
+        __syncthreads();
+        if (!ok) continue;
+        for (int i = w; i < n_th; i += 4) {
+            const double p0 = v0[(rev0 ? n_th - 1 - i : i) * 64 + lane];
+            const double p1 = v1[(rev1 ? n_th - 1 - i : i) * 64 + lane];
+            const long long o = (long long)i * n_r + k;
+            if (!fs.cplx) {
+                spec2[G.re * col + qa * per_m + o] = p0;
+                if (m > 0) spec2[G.re * col + qb * per_m + o] = p1;
+            } else if (m == 0) {
+                spec2[G.re * col + o] = p0;
+                spec2[G.im * col + o] = p1;
+            } else if (pass == 0) {
+                spec2[G.re * col + qa * per_m + o] = 0.5 * (p0 + p1);   // a^x'
+                spec2[G.im * col + qb * per_m + o] = 0.5 * (p0 - p1);   // b^y'
+            } else {
+                spec2[G.im * col + qa * per_m + o] = 0.5 * (p0 + p1);   // a^y'
+                spec2[G.re * col + qb * per_m + o] = 0.5 * (p0 - p1);   // b^x'
+            }
+        }
     }
-    double rax = 0, ray = 0, rbx = 0, rby = 0;
-    for (int ip = 0; ip < n_th; ++ip) {
-        const double s_ = S[ip], d_ = sg * D[ip];
-        const double vax = ax[ip * n_r], vay = ay[ip * n_r], vbx = bx[ip * n_r], vby = by[ip * n_r];
-        rax += s_ * vax + d_ * vby;
-        ray += s_ * vay - d_ * vbx;
-        rbx += s_ * vbx - d_ * vay;
-        rby += s_ * vby + d_ * vax;
-    }
-    *oax = rax;
-    *oay = ray;
-    *obx = rbx;
-    *oby = rby;
 }
 
 }  // namespace
@@ -319,12 +372,21 @@ hipError_t launch_recompose(const KShell& s, int count, const double* t, double*
     return hipGetLastError();
 }
 
-hipError_t launch_ftheta(const KShell& s, int count, const double* spec, double* spec2, const double* fmat,
-                         const FiltGroup* groups, int n_groups, int n_cols, int m_keep, hipStream_t st) {
-    const long long total = (long long)s.n_th * s.n_r * (m_keep + 1) * n_groups;
-    const dim3 grid((unsigned)((total + 255) / 256), (unsigned)count);
-    hipLaunchKernelGGL(k_ftheta, grid, dim3(256), 0, st, s.n_r, s.n_th, m_keep, n_groups, n_cols, spec, spec2,
-                       fmat, groups);
+hipError_t launch_ftheta(const KShell& s, int count, const double* spec, double* spec2, const FiltPlan& fp,
+                         int n_cols, int m_keep, hipStream_t st) {
+    if (fp.R < 1 || fp.R > 16 || 4 * fp.R < s.n_th) return hipErrorInvalidValue;
+    const long long cols = (long long)fp.max_groups * s.n_r;
+    const dim3 grid((unsigned)((cols + 63) / 64), (unsigned)(m_keep + 1), (unsigned)(fp.n_sets * count));
+    const size_t shm = sizeof(double) * 2 * size_t(s.n_th) * 64;
+    switch (fp.R) {
+#define X(R)                                                                                                         \
+    case R:                                                                                                          \
+        hipLaunchKernelGGL(k_ftheta<R>, grid, dim3(256), shm, st, s.n_r, s.n_th, m_keep, n_cols, spec, spec2, fp.Fb, \
+                           fp.groups, fp.sets, fp.n_sets);                                                           \
+        break;
+        X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+#undef X
+    }
     return hipGetLastError();
 }
 

@@ -33,6 +33,20 @@ struct FiltGroup {
     int re, im, set, sign;
 };
 
+// Groups [first, first + count) of the sorted group list: all real or all
+// complex (cplx) and filtered with matrix set mat.
+struct FiltSet {
+    int first, count, mat, cplx;
+};
+
+// Device view of the theta filter of one shell.
+struct FiltPlan {
+    const double* Fb;           // [mat][m][wave][N_theta][R], F^{|n|}_m rows wave-blocked
+    const FiltGroup* groups;
+    const FiltSet* sets;
+    int n_sets, max_groups, R;
+};
+
 // A matrix applied along the phi axis (n_out x n_in), wave-blocked.
 struct AxisOp {
     double* Wb = nullptr;
@@ -53,7 +67,8 @@ struct ShellHost {
     int Dr_R = 0, Hth_R = 0;
     AxisOp dph, ana, syn;                    // d_phi, Fourier analysis, Fourier synthesis
     double *rk = nullptr, *sth = nullptr, *cth = nullptr, *sph = nullptr, *cph = nullptr;
-    double *fmat = nullptr;                  // [set][m = 0..m_keep][S|D][N_theta][N_theta]
+    double *Fb = nullptr;                    // theta filter matrices, FiltPlan layout
+    int F_R = 0;                             // theta rows per wave of Fb
     double *H = nullptr, *dH = nullptr;      // static gauge
     std::vector<double> r_host, th_host, ph_host;
     KShell view(int n_v) const;
@@ -89,8 +104,11 @@ struct sg_grid {
     double *Hall = nullptr, *dHall = nullptr;   // static gauge of all shells (4, 12 fields per point)
     size_t total = 0;                 // state size in doubles
     int n_sets = 0;
-    std::vector<sg::FiltGroup> groups;
+    std::vector<sg::FiltGroup> groups;   // sorted by column set
     sg::FiltGroup* d_groups = nullptr;
+    std::vector<sg::FiltSet> fsets;
+    sg::FiltSet* d_fsets = nullptr;
+    int max_groups = 0;               // largest column set
     int n_cols = 0;                   // filter storage columns (= n_fields)
     bool tetrad = false;              // Yn: decompose on the tetrad
     double *us = nullptr, *acc = nullptr, *dbuf = nullptr;   // RK and derivative workspaces
@@ -125,8 +143,8 @@ hipError_t launch_rhs_mixed(const KShell& s, int count, const double* u, const d
                             double* out, const double* ubase, double* acc, double dt, int stage, hipStream_t st);
 hipError_t launch_decompose(const KShell& s, int count, const double* u, double* t, hipStream_t st);
 hipError_t launch_recompose(const KShell& s, int count, const double* t, double* u, hipStream_t st);
-hipError_t launch_ftheta(const KShell& s, int count, const double* spec, double* spec2, const double* fmat,
-                         const FiltGroup* groups, int n_groups, int n_cols, int m_keep, hipStream_t st);
+hipError_t launch_ftheta(const KShell& s, int count, const double* spec, double* spec2, const FiltPlan& fp,
+                         int n_cols, int m_keep, hipStream_t st);
 hipError_t launch_initial(const KShell& s, const double* g10, const double* dg, double* u,
                           double* H, hipStream_t st);
 hipError_t launch_finite_check(const double* u, size_t n, int* flag, hipStream_t st);
