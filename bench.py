@@ -21,13 +21,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-WORKLOADS = {
-    # name: (shells, n_fields, description)
-    "ks33": ([(33, 32, 64, 1.8, 11.8)], 50,
-             "perturbed Kerr-Schild M=1, 1 shell 33x32x64 r[1.8,11.8], 50 GHG fields, Yn n_f=4, lambda=4, FP64"),
-    "ks49": ([(49, 48, 96, 1.8, 11.8)], 50,
-             "perturbed Kerr-Schild M=1, 1 shell 49x48x96 r[1.8,11.8], 50 GHG fields, Yn n_f=4, lambda=4, FP64"),
+DESCRIPTIONS = {
+    "ks33": "perturbed Kerr-Schild M=1, 1 shell 33x32x64 r[1.8,11.8], 50 GHG fields, Yn n_f=4, lambda=4, FP64",
+    "ks49": "perturbed Kerr-Schild M=1, 1 shell 49x48x96 r[1.8,11.8], 50 GHG fields, Yn n_f=4, lambda=4, FP64",
 }
+
+
+def log(msg):
+    """Progress line on stderr (the JSON result is the only stdout line)."""
+    print("[bench %7.1fs] %s" % (time.perf_counter() - T_START, msg), file=sys.stderr, flush=True)
+
+
+T_START = time.perf_counter()
 
 
 def algorithmic_bytes(cls, n_r, n_th, n_ph, n_v, K):
@@ -48,17 +53,6 @@ def algorithmic_bytes(cls, n_r, n_th, n_ph, n_v, K):
     return per_fp * fp + extra
 
 
-def batch_workload(name):
-    """Shell lists of the batched workloads (grouped by size class so that
-    identical shells are adjacent)."""
-    if name == "batch64":
-        sizes = [(17, 16), (25, 24), (33, 32), (49, 48)]
-        return [(a, b, 2 * b, 1.8, 11.8) for (a, b) in sizes for _ in range(16)], 50
-    if name == "large8":
-        return [(65, 64, 128, 1.8, 21.8)] * 8, 58
-    raise ValueError(name)
-
-
 def run_variant(shells, n_v, precision, steps, warmup, seed0):
     """Throughput of one workload: seeded perturbed Kerr-Schild data on every
     shell (seed0 + shell index), filtered RK4 steps with the step graph."""
@@ -67,6 +61,7 @@ def run_variant(shells, n_v, precision, steps, warmup, seed0):
     from paper_1104_3408_amd import shellspec as ss
     from paper_1104_3408_amd import inputs
     g = ss.ShellGrid(shells, n_fields=n_v, filter="Yn", n_f=4, courant=4.0, precision=precision)
+    log("grid of %d shells created (precision %d)" % (len(shells), precision))
     g10, extra = [], []
     for k in range(len(shells)):
         r, th, ph = g.coords(k)
@@ -80,10 +75,12 @@ def run_variant(shells, n_v, precision, steps, warmup, seed0):
     del g10, extra, ex
     g.rk_step(u, warmup)
     torch.cuda.synchronize()
+    log("initial data and %d warmup steps done" % warmup)
     t0 = time.perf_counter()
     g.rk_step(u, steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    log("%d timed steps: %.3f ms/step" % (steps, 1e3 * (t1 - t0) / steps))
     fp = sum(n_v * a * b * c for (a, b, c, _, _) in shells)
     res = {"field_points": fp, "ms_per_step": 1e3 * (t1 - t0) / steps, "value": fp * steps / (t1 - t0),
            "steps": steps, "state_finite": bool(torch.isfinite(u).all().item())}
@@ -125,7 +122,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="ks33", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="ks33", choices=sorted(DESCRIPTIONS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="skip the per-kernel HIP events")
     ap.add_argument("--no-variants", action="store_true", help="skip the mixed-precision and batched workloads")
@@ -143,12 +140,15 @@ def main():
     from paper_1104_3408_amd import inputs
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
-    shells, n_v, desc = WORKLOADS[args.workload]
+    shells, n_v = inputs.workload_shells(args.workload)
+    desc = DESCRIPTIONS[args.workload]
+    seed0 = inputs.WORKLOAD_SEED[args.workload]
     g = ss.ShellGrid(shells, n_fields=n_v, filter="Yn", n_f=4, courant=4.0)
+    log("grid created")
     g10 = []
     for k in range(len(shells)):
         r, th, ph = g.coords(k)
-        g10.append(inputs.perturbed_kerr_schild(2 + k, r, th, ph).ravel())
+        g10.append(inputs.perturbed_kerr_schild(seed0 + k, r, th, ph).ravel())
     g10 = np.concatenate(g10)
     u = torch.zeros(g.state_size, dtype=torch.float64, device="cuda")
     g.kerr_schild_data(torch.from_numpy(g10).cuda(), u)
@@ -173,6 +173,7 @@ def main():
     ms_per_step = 1e3 * elapsed / args.steps
     value = fp * args.steps / elapsed
     finite = bool(torch.isfinite(u).all().item())
+    log("timed region: %d steps, %.4f ms/step" % (args.steps, ms_per_step))
 
     out = {"metric": "field-points/s per filtered RK4 step", "value": value, "unit": "field-points/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -204,6 +205,7 @@ def main():
         out["timing_pass_ms_per_step"] = 1e3 * (t3 - t2) / args.steps
         tot = sum(k["total_ms"] for k in kern.values())
         out["kernel_time_share"] = {c: kern[c]["total_ms"] / tot for c in kern}
+        log("timing pass done, dominant kernel %s %.2f us" % (dom, kern[dom]["avg_us"]))
     if args.copy_probe_mb:
         src = torch.empty(args.copy_probe_mb * (1 << 20) // 8, dtype=torch.float64, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
@@ -216,21 +218,21 @@ def main():
         var = {}
         # same shell, angular derivatives in FP32; error vs the FP64 GPU state
         # (which matches the oracle to 1e-12) after the same number of steps
-        res, um, gm = run_variant(shells, n_v, ss.SG_PREC_FP32, args.steps, args.warmup, 2)
-        uref, _, gr = None, None, None
-        res64, uref, gr = run_variant(shells, n_v, ss.SG_PREC_FP64, args.steps, args.warmup, 2)
+        res, um, gm = run_variant(shells, n_v, ss.SG_PREC_FP32, args.steps, args.warmup, seed0)
+        res64, uref, gr = run_variant(shells, n_v, ss.SG_PREC_FP64, args.steps, args.warmup, seed0)
         d = (um - uref).abs().max().item() / uref.abs().max().item()
         res["max_rel_diff_vs_fp64_gpu"] = d
         res["speedup_vs_fp64"] = res["value"] / res64["value"]
         var["mixed_fp32_angular"] = res
         del um, uref, gm, gr
         for name, steps in (("batch64", 20), ("large8", 10)):
-            bshells, bnv = batch_workload(name)
-            r64, u64, g64 = run_variant(bshells, bnv, ss.SG_PREC_FP64, steps, 2, 4000 if name == "batch64" else 5000)
+            bshells, bnv = inputs.workload_shells(name)
+            bseed = inputs.WORKLOAD_SEED[name]
+            r64, u64, g64 = run_variant(bshells, bnv, ss.SG_PREC_FP64, steps, 2, bseed)
             u64h = u64.clone()
             del u64, g64
             torch.cuda.empty_cache()
-            r32, u32, g32 = run_variant(bshells, bnv, ss.SG_PREC_FP32, steps, 2, 4000 if name == "batch64" else 5000)
+            r32, u32, g32 = run_variant(bshells, bnv, ss.SG_PREC_FP32, steps, 2, bseed)
             r32["max_rel_diff_vs_fp64_gpu"] = (u32 - u64h).abs().max().item() / u64h.abs().max().item()
             r32["speedup_vs_fp64"] = r32["value"] / r64["value"]
             var[name] = {"shells": len(bshells), "n_fields": bnv, "fp64": r64, "mixed_fp32_angular": r32}
@@ -238,6 +240,7 @@ def main():
             torch.cuda.empty_cache()
         out["variants"] = var
     if not args.no_cpu_baseline and len(shells) == 1:
+        log("oracle step on the host")
         base, err = cpu_baseline(shells[0], g10.reshape((10,) + (shells[0][2], shells[0][1], shells[0][0])),
                                  g.info(0)[2], u1_host)
         out["cpu_baseline"] = base

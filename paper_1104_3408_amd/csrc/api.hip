@@ -109,6 +109,7 @@ sg_status check_opts(const sg_shell_desc* shells, int n_shells, const sg_options
 }
 
 void free_shell(ShellHost& s) {
+    if (!s.owns_ops) return;   // operators shared with an earlier identical shell
     for (double* p : {s.Drb, s.Hsb, s.Hab, s.dph.Wb, s.ana.Wb, s.syn.Wb, s.rk, s.sth, s.cth, s.sph, s.cph, s.Fb})
         if (p) (void)hipFree(p);
     for (float* p : {s.Hsb_f, s.Hab_f, s.dph.Wb_f, s.ana.Wb_f, s.syn.Wb_f})
@@ -311,6 +312,24 @@ sg_status shell_grid_create(const sg_shell_desc* shells, int n_shells, const sg_
         S.m_keep = std::max(0, std::min(L, L - min_nf));
         S.K = 2 * S.m_keep + 1;
         spec = std::max(spec, size_t(g->n_cols) * S.K * nt * nr);
+        // identical shells share their (read-only) device operators
+        int twin = -1;
+        for (int t = 0; t < s && twin < 0; ++t) {
+            const sg_shell_desc& e = g->sh[t].d;
+            if (e.n_r == nr && e.n_theta == nt && e.n_phi == np_ && e.r_min == S.d.r_min && e.r_max == S.d.r_max)
+                twin = t;
+        }
+        if (twin >= 0) {
+            const ShellHost& T = g->sh[twin];
+            S.Drb = T.Drb; S.Hsb = T.Hsb; S.Hab = T.Hab; S.Hsb_f = T.Hsb_f; S.Hab_f = T.Hab_f;
+            S.Dr_R = T.Dr_R; S.Hth_R = T.Hth_R;
+            S.dph = T.dph; S.ana = T.ana; S.syn = T.syn;
+            S.rk = T.rk; S.sth = T.sth; S.cth = T.cth; S.sph = T.sph; S.cph = T.cph;
+            S.Fb = T.Fb; S.F_R = T.F_R;
+            S.owns_ops = false;
+            g->sh.push_back(S);
+            continue;
+        }
         g->sh.push_back(S);
         ShellHost& H = g->sh.back();
         std::vector<double> sth(nt), cth(nt), sph(np_), cph(np_);

@@ -39,18 +39,22 @@ namespace {
 
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
-// d_r: 64 lines per workgroup; wave w computes k = w R + r, r < R.
+// d_r: 64 lines per workgroup; wave w computes k = w R + r, r < R.  The tile
+// is [n_r][65]: the odd row stride keeps the transposing stores and loads of
+// consecutive k (consecutive threads) on different LDS banks.
+constexpr int kDrStride = 65;
+
 template <int R>
 __global__ __launch_bounds__(256) void k_dr(const double* __restrict__ in, double* __restrict__ out,
                                             const double* __restrict__ Db, int n_r, long long n_lines) {
-    extern __shared__ double sm[];   // [n_r][64]
+    extern __shared__ double sm[];   // [n_r][kDrStride]
     const long long line0 = (long long)blockIdx.x * 64;
     const int nl = (int)min((long long)64, n_lines - line0);
     const double* src = in + line0 * n_r;
     const int ne = nl * n_r;
     for (int e = threadIdx.x; e < 64 * n_r; e += 256) {
         const int l = e / n_r, k = e - l * n_r;
-        sm[k * 64 + l] = (e < ne) ? src[e] : 0.0;
+        sm[k * kDrStride + l] = (e < ne) ? src[e] : 0.0;
     }
     __syncthreads();
     const int lane = threadIdx.x & 63;
@@ -60,7 +64,7 @@ __global__ __launch_bounds__(256) void k_dr(const double* __restrict__ in, doubl
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[r] = 0.0;
     for (int kk = 0; kk < n_r; ++kk) {
-        const double v = sm[kk * 64 + lane];
+        const double v = sm[kk * kDrStride + lane];
         const double* d = Dw + kk * R;
 #pragma unroll
         for (int r = 0; r < R; ++r) acc[r] = fma(d[r], v, acc[r]);
@@ -69,13 +73,13 @@ __global__ __launch_bounds__(256) void k_dr(const double* __restrict__ in, doubl
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int k = w * R + r;
-        if (k < n_r) sm[k * 64 + lane] = acc[r];
+        if (k < n_r) sm[k * kDrStride + lane] = acc[r];
     }
     __syncthreads();
     double* dst = out + line0 * n_r;
     for (int e = threadIdx.x; e < ne; e += 256) {
         const int l = e / n_r, k = e - l * n_r;
-        dst[e] = sm[k * 64 + l];
+        dst[e] = sm[k * kDrStride + l];
     }
 }
 
@@ -146,59 +150,71 @@ __global__ __launch_bounds__(256) void k_dtheta(const double* __restrict__ in, O
 
 // out[f][q][c] = sum_r W[q][r] (in[f][r][c] - m_c),  m_c = mean of column c
 // over r if center, else 0.  grid: (ceil(ncol/64), n_fields); in pass p wave
-// w computes rows q = (p * 4 + w) * R + r.
-template <int R, typename I, typename T, typename O>
-__global__ __launch_bounds__(256) void k_axis(const I* __restrict__ in, O* __restrict__ out,
+// w computes rows q = (p * 4 + w) * R + r.  Thread (w, c) loads rows
+// r = w, w + 4, ... of column c once; the column mean is formed in FP64 from
+// the four waves' partial sums.  FP64 tiles keep the raw values and subtract
+// the mean per lane; FP32 tiles store (value - mean) rounded once, so the
+// rounding is relative to the deviation from the mean.
+constexpr int kAxisMaxIn = 128;
+
+template <int R, typename T, typename O>
+__global__ __launch_bounds__(256) void k_axis(const double* __restrict__ in, O* __restrict__ out,
                                               const T* __restrict__ Wb, int n_in, int n_out, int passes,
                                               long long ncol, int center) {
-    extern __shared__ double smd[];  // [n_in][64] in T
+    extern __shared__ double smd[];  // tile [n_in][64] in T, then partial sums [4][64] in FP64
     T* sm = reinterpret_cast<T*>(smd);
+    double* spart = reinterpret_cast<double*>(sm + n_in * 64);
     const long long c0 = (long long)blockIdx.x * 64;
     const int nc = (int)min((long long)64, ncol - c0);
     const int f = blockIdx.y;
-    const I* src = in + (long long)f * n_in * ncol + c0;
+    const double* src = in + (long long)f * n_in * ncol + c0;
     const int lane = threadIdx.x & 63;
     const int w = wave_id();
-    // Column mean over the axis (center != 0), in FP64.  FP64 tiles keep the
-    // raw values and subtract per lane; FP32 tiles store (value - mean) rounded
-    // once, so the rounding is relative to the deviation from the mean.
+    const bool colok = lane < nc;
     double m = 0.0;
-    if (center && sizeof(T) == 8) {
-        if (c0 + lane < ncol)
-            for (int r = 0; r < n_in; ++r) m += (double)src[(long long)r * ncol + lane];
-        m /= n_in;
-    }
-    double* smean = reinterpret_cast<double*>(sm + n_in * 64);   // FP32 tiles only
-    if (sizeof(T) == 4) {
-        if (threadIdx.x < 64) {
-            double t = 0.0;
-            if (center && c0 + threadIdx.x < ncol)
-                for (int r = 0; r < n_in; ++r) t += (double)src[(long long)r * ncol + threadIdx.x];
-            smean[threadIdx.x] = t / n_in;
+    if (sizeof(T) == 8 || !center) {
+        double part = 0.0;
+        for (int r = w; r < n_in; r += 4) {
+            const double v = colok ? src[(long long)r * ncol + lane] : 0.0;
+            part += v;
+            sm[r * 64 + lane] = (T)v;
+        }
+        if (center) spart[w * 64 + lane] = part;
+        __syncthreads();
+        if (center) m = (spart[lane] + spart[64 + lane] + spart[128 + lane] + spart[192 + lane]) / n_in;
+    } else {
+        double v[kAxisMaxIn / 4];
+        double part = 0.0;
+#pragma unroll
+        for (int t = 0; t < kAxisMaxIn / 4; ++t) {
+            const int r = w + 4 * t;
+            v[t] = (r < n_in && colok) ? src[(long long)r * ncol + lane] : 0.0;
+            part += v[t];
+        }
+        spart[w * 64 + lane] = part;
+        __syncthreads();
+        const double mc = (spart[lane] + spart[64 + lane] + spart[128 + lane] + spart[192 + lane]) / n_in;
+#pragma unroll
+        for (int t = 0; t < kAxisMaxIn / 4; ++t) {
+            const int r = w + 4 * t;
+            if (r < n_in) sm[r * 64 + lane] = (T)(v[t] - mc);
         }
         __syncthreads();
     }
-    for (int e = threadIdx.x; e < n_in * 64; e += 256) {
-        const int r = e >> 6, c = e & 63;
-        T v = (T)0;
-        if (c < nc) v = (sizeof(T) == 4) ? (T)((double)src[(long long)r * ncol + c] - smean[c])
-                                         : (T)src[(long long)r * ncol + c];
-        sm[e] = v;
-    }
-    __syncthreads();
     O* dst = out + (long long)f * n_out * ncol + c0;
+    const T mt = (T)m;
     for (int p = 0; p < passes; ++p) {
         const T* Ww = Wb + (long long)(p * 4 + w) * n_in * R;
         T acc[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) acc[r] = (T)0;
         for (int ri = 0; ri < n_in; ++ri) {
-            const T v = sm[ri * 64 + lane] - (T)m;   // m = 0 for FP32 tiles
+            const T v = sm[ri * 64 + lane] - mt;   // mt = 0 for FP32 tiles
             const T* wr = Ww + ri * R;
 #pragma unroll
             for (int r = 0; r < R; ++r) acc[r] = fma(wr[r], v, acc[r]);
         }
-        if (lane < nc) {
+        if (colok) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int q = (p * 4 + w) * R + r;
@@ -255,7 +271,7 @@ void blocked_shape(int n_out, int& R, int& passes) {
 hipError_t launch_dr(const KShell& s, const double* in, double* out, int n_fields, hipStream_t st) {
     const long long n_lines = (long long)n_fields * s.npts / s.n_r;
     const unsigned blocks = (unsigned)((n_lines + 63) / 64);
-    const size_t shm = sizeof(double) * size_t(s.n_r) * 64;
+    const size_t shm = sizeof(double) * size_t(s.n_r) * kDrStride;
     switch (s.Dr_R) {
 #define X(R) case R: hipLaunchKernelGGL(k_dr<R>, dim3(blocks), dim3(256), shm, st, in, out, s.Drb, s.n_r, n_lines); break;
         SG_R_CASES(X)
@@ -288,13 +304,14 @@ hipError_t launch_dtheta_f32(const KShell& s, const double* in, float* out, int 
     return dtheta_t<float, float>(s, in, out, s.Hsb_f, s.Hab_f, n_fields, st);
 }
 
-template <typename I, typename T, typename O>
-static hipError_t axis_t(const AxisOp& op, const T* Wb, const I* in, O* out, long long ncol, int n_fields,
+template <typename T, typename O>
+static hipError_t axis_t(const AxisOp& op, const T* Wb, const double* in, O* out, long long ncol, int n_fields,
                          int center, hipStream_t st) {
+    if (op.n_in > kAxisMaxIn) return hipErrorInvalidValue;
     const unsigned bx = (unsigned)((ncol + 63) / 64);
-    const size_t shm = sizeof(T) * size_t(op.n_in) * 64 + (sizeof(T) == 4 ? 64 * sizeof(double) : 0);
+    const size_t shm = sizeof(T) * size_t(op.n_in) * 64 + 4 * 64 * sizeof(double);
     switch (op.R) {
-#define X(R) case R: hipLaunchKernelGGL((k_axis<R, I, T, O>), dim3(bx, n_fields), dim3(256), shm, st, in, out, Wb, op.n_in, op.n_out, op.passes, ncol, center); break;
+#define X(R) case R: hipLaunchKernelGGL((k_axis<R, T, O>), dim3(bx, n_fields), dim3(256), shm, st, in, out, Wb, op.n_in, op.n_out, op.passes, ncol, center); break;
         SG_R_CASES(X)
 #undef X
         default: return hipErrorInvalidValue;
@@ -304,22 +321,12 @@ static hipError_t axis_t(const AxisOp& op, const T* Wb, const I* in, O* out, lon
 
 hipError_t launch_axis(const AxisOp& op, const double* in, double* out, long long ncol, int n_fields, int center,
                        hipStream_t st) {
-    return axis_t<double, double, double>(op, op.Wb, in, out, ncol, n_fields, center, st);
+    return axis_t<double, double>(op, op.Wb, in, out, ncol, n_fields, center, st);
 }
 
 hipError_t launch_axis_f32(const AxisOp& op, const double* in, float* out, long long ncol, int n_fields, int center,
                            hipStream_t st) {
-    return axis_t<double, float, float>(op, op.Wb_f, in, out, ncol, n_fields, center, st);
-}
-
-hipError_t launch_axis_ff(const AxisOp& op, const float* in, float* out, long long ncol, int n_fields,
-                          hipStream_t st) {
-    return axis_t<float, float, float>(op, op.Wb_f, in, out, ncol, n_fields, 0, st);
-}
-
-hipError_t launch_axis_fd(const AxisOp& op, const float* in, double* out, long long ncol, int n_fields,
-                          hipStream_t st) {
-    return axis_t<float, float, double>(op, op.Wb_f, in, out, ncol, n_fields, 0, st);
+    return axis_t<float, float>(op, op.Wb_f, in, out, ncol, n_fields, center, st);
 }
 
 hipError_t launch_chain(const KShell& s, double* du, int n_fields, hipStream_t st) {

@@ -70,6 +70,7 @@ struct ShellHost {
     double *Fb = nullptr;                    // theta filter matrices, FiltPlan layout
     int F_R = 0;                             // theta rows per wave of Fb
     double *H = nullptr, *dH = nullptr;      // static gauge
+    bool owns_ops = true;                    // false: operators belong to an earlier identical shell
     std::vector<double> r_host, th_host, ph_host;
     KShell view(int n_v) const;
 };
@@ -127,9 +128,6 @@ hipError_t launch_dtheta(const KShell& s, const double* in, double* out, int n_f
 hipError_t launch_dtheta_f32(const KShell& s, const double* in, float* out, int n_fields, hipStream_t st);
 hipError_t launch_axis_f32(const AxisOp& op, const double* in, float* out, long long ncol, int n_fields, int center,
                            hipStream_t st);
-hipError_t launch_axis_ff(const AxisOp& op, const float* in, float* out, long long ncol, int n_fields, hipStream_t st);
-hipError_t launch_axis_fd(const AxisOp& op, const float* in, double* out, long long ncol, int n_fields,
-                          hipStream_t st);
 hipError_t launch_axis(const AxisOp& op, const double* in, double* out, long long ncol, int n_fields, int center,
                        hipStream_t st);
 std::vector<double> block_operator(const std::vector<double>& W, int n_out, int n_in, int R, int passes);

@@ -13,15 +13,26 @@ namespace sg {
 
 namespace {
 
-__device__ __forceinline__ int pr(int a, int b) {
+__host__ __device__ constexpr int pr(int a, int b) {
     // symmetric pair index, order tt tx ty tz xx xy xz yy yz zz
     const int lo = a < b ? a : b, hi = a < b ? b : a;
     return lo == 0 ? hi : (lo == 1 ? 3 + hi : (lo == 2 ? 5 + hi : 9));
 }
 
-// Symmetric pairs (a, b), a <= b, in storage order.
-__constant__ int kPA[10] = {0, 0, 0, 0, 1, 1, 1, 2, 2, 3};
-__constant__ int kPB[10] = {0, 1, 2, 3, 1, 2, 3, 2, 3, 3};
+// Symmetric pair q = (a, b), a <= b, in storage order.
+__host__ __device__ constexpr int pair_a(int q) { return q < 4 ? 0 : (q < 7 ? 1 : (q < 9 ? 2 : 3)); }
+__host__ __device__ constexpr int pair_b(int q) { return q < 4 ? q : (q < 7 ? q - 3 : (q < 9 ? q - 5 : 3)); }
+static_assert(pair_a(5) == 1 && pair_b(5) == 2 && pair_a(8) == 2 && pair_b(8) == 3, "pair order");
+
+template <int Q>
+struct PairC {
+    static constexpr int value = Q;
+};
+
+// Waves per SIMD the register allocation must allow (2: 256 VGPRs, 3: 168).
+#ifndef SG_RHS_WAVES_PER_SIMD
+#define SG_RHS_WAVES_PER_SIMD 2
+#endif
 
 constexpr int kPts = 64;      // grid points per workgroup
 constexpr int kWaves = 5;     // wave w owns symmetric pairs 2w and 2w+1
@@ -34,7 +45,7 @@ constexpr int kWaves = 5;     // wave w owns symmetric pairs 2w and 2w+1
 // derivative terms of d_t g_ab, d_t Pi_ab and d_t Phi_xab, the boundary
 // operator (which couples only fields of one pair) and the RK4 stage update.
 template <int NV, typename TD>
-__global__ __launch_bounds__(320) void k_rhs(KShell s, const double* __restrict__ u,
+__global__ __launch_bounds__(kWaves * 64, SG_RHS_WAVES_PER_SIMD) void k_rhs(KShell s, const double* __restrict__ u,
                                              const double* __restrict__ du, const TD* __restrict__ dang, int cart,
                                              double* __restrict__ out, const double* __restrict__ ubase,
                                              double* __restrict__ acc, double dt, int stage, long long blk) {
@@ -143,7 +154,7 @@ __global__ __launch_bounds__(320) void k_rhs(KShell s, const double* __restrict_
     if (w == 0) {
 #pragma unroll
         for (int q = 0; q < 10; ++q) {
-            const int a = kPA[q], b = kPB[q];
+            const int a = pair_a(q), b = pair_b(q);
             sdtg[q][lane] = -al * PI(a, b) + bu[0] * PH(0, a, b) + bu[1] * PH(1, a, b) + bu[2] * PH(2, a, b);
         }
     } else if (w == 1) {
@@ -213,69 +224,64 @@ __global__ __launch_bounds__(320) void k_rhs(KShell s, const double* __restrict_
     __syncthreads();
     const double nC = nu[0] * sC[0][lane] + nu[1] * sC[1][lane] + nu[2] * sC[2][lane] + nu[3] * sC[3][lane];
 
-    // ---- the wave's two symmetric pairs, one after the other --------------------
-#pragma unroll 1
-    for (int h = 0; h < 2; ++h) {
-        const int q = 2 * w + h;
-        const int a = kPA[q], b = kPB[q];
+    // ---- the wave's two symmetric pairs; the pair index is a compile-time
+    // constant in each instance of the body, so every LDS offset and every
+    // branch on the indices folds away -----------------------------------------
+    auto pair = [&](auto QC) {
+        constexpr int q = decltype(QC)::value;
+        constexpr int a = pair_a(q), b = pair_b(q);
+        // Cartesian derivatives of g_ab, Pi_ab, Phi_xab (loads issued first)
+        double dg[3] = {0.0, 0.0, 0.0}, dP[3] = {0.0, 0.0, 0.0}, dF[3][3] = {};
+        if (ok) {
+            cartd(q, dg);
+            cartd(10 + q, dP);
+#pragma unroll
+            for (int x = 0; x < 3; ++x) cartd(20 + 10 * x + q, dF[x]);
+        }
         // quadratic bracket of eq. Pidot,
         //   g^cd (gamma^ij Phi_iac Phi_jbd - Pi_ac Pi_bd) - g^cd g^ef Gamma_ace Gamma_bdf
         //   = Phi_xac Z_xc - Pi_ac V_c - Gamma_ace Y^ce,
         // with Z_xc = g^cd gamma^xy Phi_ybd, V_c = g^cd Pi_bd and
-        // Y = G Gamma_b G (Gamma_b the 4x4 matrix Gamma_bdf); the row-a factors
-        // are streamed from LDS.
+        // Y = G Gamma_b G (Gamma_b the 4x4 matrix Gamma_bdf).
         double quad = 0.0;
         {
-            double Z[3][4], V[4];
-            {
-                double Pb[3][4], pb[4];
+            double Pb[3][4], pb[4];
 #pragma unroll
-                for (int d = 0; d < 4; ++d) {
-                    const double f0 = PH(0, b, d), f1 = PH(1, b, d), f2 = PH(2, b, d);
+            for (int d = 0; d < 4; ++d) {
+                const double f0 = PH(0, b, d), f1 = PH(1, b, d), f2 = PH(2, b, d);
 #pragma unroll
-                    for (int x = 0; x < 3; ++x) Pb[x][d] = gi[x][0] * f0 + gi[x][1] * f1 + gi[x][2] * f2;
-                    pb[d] = PI(b, d);
-                }
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-#pragma unroll
-                    for (int x = 0; x < 3; ++x)
-                        Z[x][c] = gI[c][0] * Pb[x][0] + gI[c][1] * Pb[x][1] + gI[c][2] * Pb[x][2] + gI[c][3] * Pb[x][3];
-                    V[c] = gI[c][0] * pb[0] + gI[c][1] * pb[1] + gI[c][2] * pb[2] + gI[c][3] * pb[3];
-                }
+                for (int x = 0; x < 3; ++x) Pb[x][d] = gi[x][0] * f0 + gi[x][1] * f1 + gi[x][2] * f2;
+                pb[d] = PI(b, d);
             }
-            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
-                quad += PH(0, a, c) * Z[0][c] + PH(1, a, c) * Z[1][c] + PH(2, a, c) * Z[2][c] - PI(a, c) * V[c];
+            for (int c = 0; c < 4; ++c) {
+                double zc[3];
+#pragma unroll
+                for (int x = 0; x < 3; ++x)
+                    zc[x] = gI[c][0] * Pb[x][0] + gI[c][1] * Pb[x][1] + gI[c][2] * Pb[x][2] + gI[c][3] * Pb[x][3];
+                const double vc = gI[c][0] * pb[0] + gI[c][1] * pb[1] + gI[c][2] * pb[2] + gI[c][3] * pb[3];
+                quad += PH(0, a, c) * zc[0] + PH(1, a, c) * zc[1] + PH(2, a, c) * zc[2] - PI(a, c) * vc;
+            }
         }
-        __builtin_amdgcn_sched_barrier(0);
         {
-            double Y[4][4];
-            {
-                double X[4][4];   // X[d][f] = g^de Gamma_bef
+            double X[4][4];   // X[d][f] = g^de Gamma_bef
 #pragma unroll
-                for (int f = 0; f < 4; ++f) {
-                    double gb[4];
+            for (int f = 0; f < 4; ++f) {
+                double gb[4];
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) gb[e] = Gam(b, e, f);
-#pragma unroll
-                    for (int d = 0; d < 4; ++d)
-                        X[d][f] = gI[d][0] * gb[0] + gI[d][1] * gb[1] + gI[d][2] * gb[2] + gI[d][3] * gb[3];
-                }
+                for (int e = 0; e < 4; ++e) gb[e] = Gam(b, e, f);
 #pragma unroll
                 for (int d = 0; d < 4; ++d)
-#pragma unroll
-                    for (int c = d; c < 4; ++c)
-                        Y[d][c] = Y[c][d] = X[d][0] * gI[0][c] + X[d][1] * gI[1][c] + X[d][2] * gI[2][c] + X[d][3] * gI[3][c];
+                    X[d][f] = gI[d][0] * gb[0] + gI[d][1] * gb[1] + gI[d][2] * gb[2] + gI[d][3] * gb[3];
             }
-            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
+            for (int d = 0; d < 4; ++d)
 #pragma unroll
-                for (int e = c; e < 4; ++e) quad -= (c == e ? 1.0 : 2.0) * Gam(a, c, e) * Y[c][e];
+                for (int c = d; c < 4; ++c) {
+                    const double y = X[d][0] * gI[0][c] + X[d][1] * gI[1][c] + X[d][2] * gI[2][c] + X[d][3] * gI[3][c];
+                    quad -= (c == d ? 1.0 : 2.0) * Gam(a, d, c) * y;
+                }
         }
-        __builtin_amdgcn_sched_barrier(0);
         double nabH = 0.5 * (sdH[a][b][lane] + sdH[b][a][lane]);
 #pragma unroll
         for (int c = 0; c < 4; ++c) nabH -= sHu[c][lane] * Gam(c, a, b);
@@ -285,35 +291,21 @@ __global__ __launch_bounds__(320) void k_rhs(KShell s, const double* __restrict_
         double damp = -G(a, b) * nC;
         if (b == 0) damp += sC[a][lane] * nl0;
         if (a == 0) damp += sC[b][lane] * nl0;
-        // eq. Pidot, undifferentiated terms
+        // eq. Pidot
         double rP = 2.0 * al * quad - 2.0 * al * nabH - 0.5 * al * sv[0][lane] * Pab
                     - al * (sv[1][lane] * Fab[0] + sv[2][lane] * Fab[1] + sv[3][lane] * Fab[2]) + al * damp + bF;
-        // eq. Phidot, undifferentiated terms
+        rP += -(bu[0] * dg[0] + bu[1] * dg[1] + bu[2] * dg[2]) + (bu[0] * dP[0] + bu[1] * dP[1] + bu[2] * dP[2]);
+#pragma unroll
+        for (int x = 0; x < 3; ++x) rP -= al * (gi[x][0] * dF[x][0] + gi[x][1] * dF[x][1] + gi[x][2] * dF[x][2]);
+        // eq. Phidot
         double rF[3];
 #pragma unroll
         for (int x = 0; x < 3; ++x)
             rF[x] = 0.5 * al * sv[4 + x][lane] * Pab
-                    + al * (swu[x][0][lane] * Fab[0] + swu[x][1][lane] * Fab[1] + swu[x][2][lane] * Fab[2]) - al * Fab[x];
+                    + al * (swu[x][0][lane] * Fab[0] + swu[x][1][lane] * Fab[1] + swu[x][2][lane] * Fab[2]) - al * Fab[x]
+                    + al * dg[x] - al * dP[x] + bu[0] * dF[x][0] + bu[1] * dF[x][1] + bu[2] * dF[x][2];
         // eq. gdot
         double rg = -al * Pab + bF;
-        // derivative terms
-        if (ok) {
-            double d[3];
-            cartd(q, d);                                    // d_x g_ab
-            rP -= bu[0] * d[0] + bu[1] * d[1] + bu[2] * d[2];
-#pragma unroll
-            for (int x = 0; x < 3; ++x) rF[x] += al * d[x];
-            cartd(10 + q, d);                               // d_x Pi_ab
-            rP += bu[0] * d[0] + bu[1] * d[1] + bu[2] * d[2];
-#pragma unroll
-            for (int x = 0; x < 3; ++x) rF[x] -= al * d[x];
-#pragma unroll
-            for (int x = 0; x < 3; ++x) {
-                cartd(20 + 10 * x + q, d);                  // d_y Phi_xab
-                rF[x] += bu[0] * d[0] + bu[1] * d[1] + bu[2] * d[2];
-                rP -= al * (gi[x][0] * d[0] + gi[x][1] * d[1] + gi[x][2] * d[2]);
-            }
-        }
         // outer boundary: freeze incoming characteristic fields (App. A.3)
         if (k == s.n_r - 1) {
             const double xh[3] = {st * cp, st * sp, ct};
@@ -350,7 +342,7 @@ __global__ __launch_bounds__(320) void k_rhs(KShell s, const double* __restrict_
             emit(10 + q, rP);
 #pragma unroll
             for (int x = 0; x < 3; ++x) emit(20 + 10 * x + q, rF[x]);
-            if (NV == 58 && w == 4 && h == 1) {
+            if constexpr (NV == 58 && q == 9) {
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     emit(50 + c, sdH[0][c][lane]);   // d_t H_c = Q_c
@@ -358,6 +350,13 @@ __global__ __launch_bounds__(320) void k_rhs(KShell s, const double* __restrict_
                 }
             }
         }
+    };
+    switch (w) {
+        case 0: pair(PairC<0>{}); pair(PairC<1>{}); break;
+        case 1: pair(PairC<2>{}); pair(PairC<3>{}); break;
+        case 2: pair(PairC<4>{}); pair(PairC<5>{}); break;
+        case 3: pair(PairC<6>{}); pair(PairC<7>{}); break;
+        default: pair(PairC<8>{}); pair(PairC<9>{}); break;
     }
 }
 

@@ -111,3 +111,24 @@ def gauge_perturbation(seed, r, theta, phi, amp=1e-6, r0=6.0, width=1.0):
     x, y, z = spherical_to_cartesian(r, theta, phi)
     p = smooth_perturbation(seed, x, y, z, 8, amp, r0, width)
     return p[:4], p[4:]
+
+
+# Shell lists of the benchmark workloads: (N_r, N_theta, N_phi, r_min, r_max),
+# identical shells adjacent so that they run as one batch.  Shell k draws its
+# perturbation with seed base + k (gauge fields: base + 1000 + k).
+WORKLOAD_SEED = {"ks33": 2, "ks49": 2, "batch64": 4000, "large8": 5000}
+
+
+def workload_shells(name):
+    """(shells, n_fields) of a named workload."""
+    if name == "ks33":
+        return [(33, 32, 64, 1.8, 11.8)], 50
+    if name == "ks49":
+        return [(49, 48, 96, 1.8, 11.8)], 50
+    if name == "batch64":
+        sizes = [(17, 16), (25, 24), (33, 32), (49, 48)]
+        return [(a, b, 2 * b, 1.8, 11.8) for (a, b) in sizes for _ in range(16)], 50
+    if name == "large8":
+        return [(65, 64, 128, 1.8, 21.8)] * 8, 58
+    raise ValueError(name)
+
