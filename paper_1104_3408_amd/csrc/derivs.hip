@@ -52,8 +52,12 @@ __global__ __launch_bounds__(256) void k_dr(const double* __restrict__ in, doubl
     const int nl = (int)min((long long)64, n_lines - line0);
     const double* src = in + line0 * n_r;
     const int ne = nl * n_r;
+    // e = l n_r + k split without an integer division: e < 64 n_r <= 5120, so
+    // (e + 1/2)/n_r in FP32 is at least 1/(2 n_r) from an integer and its
+    // rounding error (< 1e-5) cannot move the floor
+    const float inv_nr = 1.0f / (float)n_r;
     for (int e = threadIdx.x; e < 64 * n_r; e += 256) {
-        const int l = e / n_r, k = e - l * n_r;
+        const int l = (int)(((float)e + 0.5f) * inv_nr), k = e - l * n_r;
         sm[k * kDrStride + l] = (e < ne) ? src[e] : 0.0;
     }
     __syncthreads();
@@ -78,7 +82,7 @@ __global__ __launch_bounds__(256) void k_dr(const double* __restrict__ in, doubl
     __syncthreads();
     double* dst = out + line0 * n_r;
     for (int e = threadIdx.x; e < ne; e += 256) {
-        const int l = e / n_r, k = e - l * n_r;
+        const int l = (int)(((float)e + 0.5f) * inv_nr), k = e - l * n_r;
         dst[e] = sm[k * kDrStride + l];
     }
 }
@@ -96,24 +100,29 @@ __global__ __launch_bounds__(256) void k_dtheta(const double* __restrict__ in, O
     const int half = n_ph / 2;
     const long long plane = (long long)n_th * n_r;
     const long long c0 = (long long)blockIdx.x * 64;
-    for (int e = threadIdx.x; e < n_th * 64; e += 256) {
-        const int ip = e >> 6, cl = e & 63;
-        const long long c = c0 + cl;
+    // this thread's column (fixed: the loop steps by a multiple of 64)
+    const int lane = threadIdx.x & 63;
+    const long long c = c0 + lane;
+    const bool cok = c < n_cols;
+    long long f = 0;
+    int jp = 0, k = 0;
+    if (cok) {
+        const long long fj = c / n_r;
+        k = (int)(c - fj * n_r);
+        f = fj / half;
+        jp = (int)(fj - f * half);
+    }
+    const double* base = in + f * n_ph * plane + (long long)jp * plane + k;
+    for (int ip = threadIdx.x >> 6; ip < n_th; ip += 4) {
         double a = 0.0, b = 0.0;
-        if (c < n_cols) {
-            const long long fj = c / n_r;
-            const int k = (int)(c - fj * n_r);
-            const long long f = fj / half;
-            const int jp = (int)(fj - f * half);
-            const double* base = in + f * n_ph * plane + (long long)ip * n_r + k;
-            a = base[jp * plane];
-            b = base[(jp + half) * plane];
+        if (cok) {
+            a = base[(long long)ip * n_r];
+            b = base[half * plane + (long long)ip * n_r];
         }
-        sS[e] = (T)(a + b);
-        sA[e] = (T)(a - b);
+        sS[ip * 64 + lane] = (T)(a + b);
+        sA[ip * 64 + lane] = (T)(a - b);
     }
     __syncthreads();
-    const int lane = threadIdx.x & 63;
     const int w = wave_id();
     const T* Sw = Hsb + (long long)w * n_th * R;
     const T* Aw = Hab + (long long)w * n_th * R;
@@ -130,12 +139,7 @@ __global__ __launch_bounds__(256) void k_dtheta(const double* __restrict__ in, O
             aA[r] = fma(ha[r], av, aA[r]);
         }
     }
-    const long long c = c0 + lane;
-    if (c < n_cols) {
-        const long long fj = c / n_r;
-        const int k = (int)(c - fj * n_r);
-        const long long f = fj / half;
-        const int jp = (int)(fj - f * half);
+    if (cok) {
         O* o = out + f * n_ph * plane + jp * plane + k;
 #pragma unroll
         for (int r = 0; r < R; ++r) {

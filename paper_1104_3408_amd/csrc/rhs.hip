@@ -63,6 +63,7 @@ __global__ __launch_bounds__(kWaves * 64, SG_RHS_WAVES_PER_SIMD) void k_rhs(KShe
         s.dH += (long long)blockIdx.y * 12 * s.npts;
     }
     __shared__ double su[NV][kPts];          // state of the 64 points
+    __shared__ double sdu[3][NV][kPts];      // Cartesian first derivatives d_x u
     __shared__ double sH[4][kPts];           // H_a
     __shared__ double sdH[4][4][kPts];       // d_a H_b (a = t from the state or 0)
     __shared__ double sdtg[10][kPts];        // d_t g_ab, eq. gdot
@@ -78,14 +79,46 @@ __global__ __launch_bounds__(kWaves * 64, SG_RHS_WAVES_PER_SIMD) void k_rhs(KShe
     const long long p = p0 + lane;
     const bool ok = p < np;
 
-    // ---- stage variables; points past the end get Minkowski data -----------
-    for (int e = threadIdx.x; e < NV * kPts; e += kWaves * 64) {
-        const int f = e >> 6, l = e & 63;
-        const long long q = p0 + l;
-        double v;
-        if (q < np) v = u[(long long)f * np + q];
-        else v = (f == 0) ? -1.0 : ((f == 4 || f == 7 || f == 9) ? 1.0 : 0.0);
-        su[f][l] = v;
+    // ---- per-thread geometry (every thread's point is its lane: the staging
+    // loops below step by a multiple of 64) ------------------------------------
+    const int k = ok ? (int)(p % s.n_r) : 0;
+    const int i = ok ? (int)((p / s.n_r) % s.n_th) : 0;
+    const int j = ok ? (int)(p / ((long long)s.n_r * s.n_th)) : 0;
+    const double st = s.sth[i], ct = s.cth[i], sp = s.sph[j], cp = s.cph[j];
+
+    // ---- stage the variables and their derivatives in one burst; points past
+    // the end get Minkowski data and zero derivatives. Derivatives are turned
+    // into Cartesian ones here: chain rule of Sec. 2.2 (eq. dvdx) with the
+    // analytic Jacobian d(r, theta, phi)/d(x, y, z). ----------------------------
+    {
+        const double ir = ok ? 1.0 / s.rk[k] : 0.0, irs = ok ? ir / st : 0.0;
+        const double J[3][3] = {{st * cp, ct * cp * ir, -sp * irs},
+                                {st * sp, ct * sp * ir, cp * irs},
+                                {ct, -st * ir, 0.0}};
+#pragma unroll
+        for (int t = 0; t < (NV + kWaves - 1) / kWaves; ++t) {
+            const int f = w + t * kWaves;
+            if (f >= NV) break;
+            const long long q = (long long)f * np + p;
+            double v, d0 = 0.0, d1 = 0.0, d2 = 0.0;
+            if (ok) {
+                v = u[q];
+                d0 = du[q];
+                d1 = (double)dang[q];
+                d2 = (double)dang[blk + q];
+            } else {
+                v = (f == 0) ? -1.0 : ((f == 4 || f == 7 || f == 9) ? 1.0 : 0.0);
+            }
+            su[f][lane] = v;
+            if (cart) {
+                sdu[0][f][lane] = d0;
+                sdu[1][f][lane] = d1;
+                sdu[2][f][lane] = d2;
+            } else {
+#pragma unroll
+                for (int x = 0; x < 3; ++x) sdu[x][f][lane] = J[x][0] * d0 + J[x][1] * d1 + J[x][2] * d2;
+            }
+        }
     }
     if (NV == 50) {
         for (int e = threadIdx.x; e < 16 * kPts; e += kWaves * 64) {
@@ -102,11 +135,7 @@ __global__ __launch_bounds__(kWaves * 64, SG_RHS_WAVES_PER_SIMD) void k_rhs(KShe
     }
     __syncthreads();
 
-    // ---- per-thread geometry and 3+1 split (eqs. normal, abgfromgab) -------
-    const int k = ok ? (int)(p % s.n_r) : 0;
-    const int i = ok ? (int)((p / s.n_r) % s.n_th) : 0;
-    const int j = ok ? (int)(p / ((long long)s.n_r * s.n_th)) : 0;
-    const double st = s.sth[i], ct = s.cth[i], sp = s.sph[j], cp = s.cph[j];
+    // ---- 3+1 split (eqs. normal, abgfromgab) ----------------------------------
     auto G = [&](int a, int b) -> double { return su[pr(a, b)][lane]; };
     auto PI = [&](int a, int b) -> double { return su[10 + pr(a, b)][lane]; };
     auto PH = [&](int x, int a, int b) -> double { return su[20 + 10 * x + pr(a, b)][lane]; };
@@ -133,22 +162,7 @@ __global__ __launch_bounds__(kWaves * 64, SG_RHS_WAVES_PER_SIMD) void k_rhs(KShe
     }
     const double nu[4] = {ial, -bu[0] * ial, -bu[1] * ial, -bu[2] * ial};
     const double nl0 = -al;   // n_a = (-alpha, 0, 0, 0)
-    // Cartesian derivative of variable mu: chain rule of Sec. 2.2 (eq. dvdx)
-    // with the analytic Jacobian d(r, theta, phi)/d(x, y, z), formed here so
-    // that it is not live across the algebra.
-    auto cartd = [&](int mu, double d[3]) {
-        const long long q = (long long)mu * np + p;
-        // d_r in FP64; d_theta, d_phi in TD (FP32 on the mixed-precision path)
-        const double d0 = du[q], d1 = (double)dang[q], d2 = (double)dang[blk + q];
-        if (cart) {
-            d[0] = d0; d[1] = d1; d[2] = d2;
-        } else {
-            const double ir = 1.0 / s.rk[k], irs = ir / st;
-            d[0] = st * cp * d0 + ct * cp * ir * d1 - sp * irs * d2;
-            d[1] = st * sp * d0 + ct * sp * ir * d1 + cp * irs * d2;
-            d[2] = ct * d0 - st * ir * d1;
-        }
-    };
+    auto CD = [&](int x, int mu) -> double { return sdu[x][mu][lane]; };   // d_x u_mu
 
     // ---- shared per-point quantities, phase 1 --------------------------------
     if (w == 0) {
@@ -163,10 +177,8 @@ __global__ __launch_bounds__(kWaves * 64, SG_RHS_WAVES_PER_SIMD) void k_rhs(KShe
             for (int b = 0; b < 4; ++b) {
                 sH[b][lane] = su[50 + b][lane];
                 sdH[0][b][lane] = su[54 + b][lane];              // d_t H_b = Q_b
-                double d[3] = {0.0, 0.0, 0.0};
-                if (ok) cartd(50 + b, d);
 #pragma unroll
-                for (int x = 0; x < 3; ++x) sdH[x + 1][b][lane] = d[x];
+                for (int x = 0; x < 3; ++x) sdH[x + 1][b][lane] = CD(x, 50 + b);
             }
         }
     } else if (w == 2) {
@@ -224,63 +236,20 @@ __global__ __launch_bounds__(kWaves * 64, SG_RHS_WAVES_PER_SIMD) void k_rhs(KShe
     __syncthreads();
     const double nC = nu[0] * sC[0][lane] + nu[1] * sC[1][lane] + nu[2] * sC[2][lane] + nu[3] * sC[3][lane];
 
-    // ---- the wave's two symmetric pairs; the pair index is a compile-time
-    // constant in each instance of the body, so every LDS offset and every
-    // branch on the indices folds away -----------------------------------------
-    auto pair = [&](auto QC) {
-        constexpr int q = decltype(QC)::value;
-        constexpr int a = pair_a(q), b = pair_b(q);
-        // Cartesian derivatives of g_ab, Pi_ab, Phi_xab (loads issued first)
-        double dg[3] = {0.0, 0.0, 0.0}, dP[3] = {0.0, 0.0, 0.0}, dF[3][3] = {};
-        if (ok) {
-            cartd(q, dg);
-            cartd(10 + q, dP);
+    // sources, derivative terms, boundary operator and stage update of pair
+    // (a, b), given its quadratic bracket
+    auto pair_tail = [&](auto AC, auto BC, double quad) {
+        constexpr int a = decltype(AC)::value < decltype(BC)::value ? decltype(AC)::value : decltype(BC)::value;
+        constexpr int b = decltype(AC)::value < decltype(BC)::value ? decltype(BC)::value : decltype(AC)::value;
+        constexpr int q = pr(a, b);
+        // Cartesian derivatives of g_ab, Pi_ab, Phi_xab
+        double dg[3], dP[3], dF[3][3];
 #pragma unroll
-            for (int x = 0; x < 3; ++x) cartd(20 + 10 * x + q, dF[x]);
-        }
-        // quadratic bracket of eq. Pidot,
-        //   g^cd (gamma^ij Phi_iac Phi_jbd - Pi_ac Pi_bd) - g^cd g^ef Gamma_ace Gamma_bdf
-        //   = Phi_xac Z_xc - Pi_ac V_c - Gamma_ace Y^ce,
-        // with Z_xc = g^cd gamma^xy Phi_ybd, V_c = g^cd Pi_bd and
-        // Y = G Gamma_b G (Gamma_b the 4x4 matrix Gamma_bdf).
-        double quad = 0.0;
-        {
-            double Pb[3][4], pb[4];
+        for (int x = 0; x < 3; ++x) {
+            dg[x] = CD(x, q);
+            dP[x] = CD(x, 10 + q);
 #pragma unroll
-            for (int d = 0; d < 4; ++d) {
-                const double f0 = PH(0, b, d), f1 = PH(1, b, d), f2 = PH(2, b, d);
-#pragma unroll
-                for (int x = 0; x < 3; ++x) Pb[x][d] = gi[x][0] * f0 + gi[x][1] * f1 + gi[x][2] * f2;
-                pb[d] = PI(b, d);
-            }
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                double zc[3];
-#pragma unroll
-                for (int x = 0; x < 3; ++x)
-                    zc[x] = gI[c][0] * Pb[x][0] + gI[c][1] * Pb[x][1] + gI[c][2] * Pb[x][2] + gI[c][3] * Pb[x][3];
-                const double vc = gI[c][0] * pb[0] + gI[c][1] * pb[1] + gI[c][2] * pb[2] + gI[c][3] * pb[3];
-                quad += PH(0, a, c) * zc[0] + PH(1, a, c) * zc[1] + PH(2, a, c) * zc[2] - PI(a, c) * vc;
-            }
-        }
-        {
-            double X[4][4];   // X[d][f] = g^de Gamma_bef
-#pragma unroll
-            for (int f = 0; f < 4; ++f) {
-                double gb[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) gb[e] = Gam(b, e, f);
-#pragma unroll
-                for (int d = 0; d < 4; ++d)
-                    X[d][f] = gI[d][0] * gb[0] + gI[d][1] * gb[1] + gI[d][2] * gb[2] + gI[d][3] * gb[3];
-            }
-#pragma unroll
-            for (int d = 0; d < 4; ++d)
-#pragma unroll
-                for (int c = d; c < 4; ++c) {
-                    const double y = X[d][0] * gI[0][c] + X[d][1] * gI[1][c] + X[d][2] * gI[2][c] + X[d][3] * gI[3][c];
-                    quad -= (c == d ? 1.0 : 2.0) * Gam(a, d, c) * y;
-                }
+            for (int y = 0; y < 3; ++y) dF[y][x] = CD(x, 20 + 10 * y + q);
         }
         double nabH = 0.5 * (sdH[a][b][lane] + sdH[b][a][lane]);
 #pragma unroll
@@ -320,7 +289,8 @@ __global__ __launch_bounds__(kWaves * 64, SG_RHS_WAVES_PER_SIMD) void k_rhs(KShe
             for (int x = 0; x < 3; ++x) rF[x] = xh[x] * inorm * wv;
         }
         if (ok) {
-            auto emit = [&](int mu, double kv) {
+            auto emit = [&](int m, double kv) {
+                const int mu = q + 10 * m;
                 const long long o = (long long)mu * np + p;
                 if (stage == 0) {
                     out[o] = kv;
@@ -329,34 +299,105 @@ __global__ __launch_bounds__(kWaves * 64, SG_RHS_WAVES_PER_SIMD) void k_rhs(KShe
                     acc[o] = u0 + dt * (1.0 / 6.0) * kv;
                     out[o] = u0 + 0.5 * dt * kv;
                 } else if (stage == 2) {        // k2 at us: acc += dt/3 k2, us = u + dt/2 k2
-                    acc[o] += dt * (1.0 / 3.0) * kv;
+                    acc[o] = acc[o] + dt * (1.0 / 3.0) * kv;
                     out[o] = ubase[o] + 0.5 * dt * kv;
                 } else if (stage == 3) {        // k3: acc += dt/3 k3, us = u + dt k3
-                    acc[o] += dt * (1.0 / 3.0) * kv;
+                    acc[o] = acc[o] + dt * (1.0 / 3.0) * kv;
                     out[o] = ubase[o] + dt * kv;
                 } else {                        // k4: u = acc + dt/6 k4
                     out[o] = acc[o] + dt * (1.0 / 6.0) * kv;
                 }
             };
-            emit(q, rg);
-            emit(10 + q, rP);
+            emit(0, rg);
+            emit(1, rP);
 #pragma unroll
-            for (int x = 0; x < 3; ++x) emit(20 + 10 * x + q, rF[x]);
-            if constexpr (NV == 58 && q == 9) {
+            for (int x = 0; x < 3; ++x) emit(2 + x, rF[x]);
+            if constexpr (NV == 58 && q == 6) {   // d_t H_c = Q_c, d_t Q_c = 0
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    emit(50 + c, sdH[0][c][lane]);   // d_t H_c = Q_c
-                    emit(54 + c, 0.0);               // d_t Q_c = 0
+                for (int c = 0; c < 8; ++c) {
+                    const long long o = (long long)(50 + c) * np + p;
+                    const double kv = c < 4 ? sdH[0][c][lane] : 0.0;
+                    const double u0 = su[50 + c][lane];
+                    if (stage == 0) {
+                        out[o] = kv;
+                    } else if (stage == 1) {
+                        acc[o] = u0 + dt * (1.0 / 6.0) * kv;
+                        out[o] = u0 + 0.5 * dt * kv;
+                    } else if (stage == 2) {
+                        acc[o] += dt * (1.0 / 3.0) * kv;
+                        out[o] = ubase[o] + 0.5 * dt * kv;
+                    } else if (stage == 3) {
+                        acc[o] += dt * (1.0 / 3.0) * kv;
+                        out[o] = ubase[o] + dt * kv;
+                    } else {
+                        out[o] = acc[o] + dt * (1.0 / 6.0) * kv;
+                    }
                 }
             }
         }
     };
-    switch (w) {
-        case 0: pair(PairC<0>{}); pair(PairC<1>{}); break;
-        case 1: pair(PairC<2>{}); pair(PairC<3>{}); break;
-        case 2: pair(PairC<4>{}); pair(PairC<5>{}); break;
-        case 3: pair(PairC<6>{}); pair(PairC<7>{}); break;
-        default: pair(PairC<8>{}); pair(PairC<9>{}); break;
+    // ---- the wave's two symmetric pairs (a1, b) and (a2, b) share the index b,
+    // so the b-dependent contractions of the quadratic term are formed once;
+    // all indices are compile-time constants in each instance of the body, so
+    // every LDS offset and every branch on the indices folds away -------------
+    auto wave_pairs = [&](auto BC, auto A1C, auto A2C) {
+        constexpr int b = decltype(BC)::value, a1 = decltype(A1C)::value, a2 = decltype(A2C)::value;
+        // quadratic bracket of eq. Pidot for (a, b),
+        //   g^cd (gamma^ij Phi_iac Phi_jbd - Pi_ac Pi_bd) - g^cd g^ef Gamma_ace Gamma_bdf
+        //   = Phi_xac Z_xc - Pi_ac V_c - Gamma_ace Y^ce,
+        // with Z_xc = g^cd gamma^xy Phi_ybd, V_c = g^cd Pi_bd and
+        // Y = G Gamma_b G (Gamma_b the 4x4 matrix Gamma_bdf), all of row b.
+        double quad1 = 0.0, quad2 = 0.0;
+        {
+            double Pb[3][4], pb[4];
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                const double f0 = PH(0, b, d), f1 = PH(1, b, d), f2 = PH(2, b, d);
+#pragma unroll
+                for (int x = 0; x < 3; ++x) Pb[x][d] = gi[x][0] * f0 + gi[x][1] * f1 + gi[x][2] * f2;
+                pb[d] = PI(b, d);
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                double zc[3];
+#pragma unroll
+                for (int x = 0; x < 3; ++x)
+                    zc[x] = gI[c][0] * Pb[x][0] + gI[c][1] * Pb[x][1] + gI[c][2] * Pb[x][2] + gI[c][3] * Pb[x][3];
+                const double vc = gI[c][0] * pb[0] + gI[c][1] * pb[1] + gI[c][2] * pb[2] + gI[c][3] * pb[3];
+                quad1 += PH(0, a1, c) * zc[0] + PH(1, a1, c) * zc[1] + PH(2, a1, c) * zc[2] - PI(a1, c) * vc;
+                quad2 += PH(0, a2, c) * zc[0] + PH(1, a2, c) * zc[1] + PH(2, a2, c) * zc[2] - PI(a2, c) * vc;
+            }
+        }
+        {
+            double X[4][4];   // X[d][f] = g^de Gamma_bef
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                double gb[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) gb[e] = Gam(b, e, f);
+#pragma unroll
+                for (int d = 0; d < 4; ++d)
+                    X[d][f] = gI[d][0] * gb[0] + gI[d][1] * gb[1] + gI[d][2] * gb[2] + gI[d][3] * gb[3];
+            }
+#pragma unroll
+            for (int d = 0; d < 4; ++d)
+#pragma unroll
+                for (int c = d; c < 4; ++c) {
+                    const double y = (c == d ? 1.0 : 2.0) *
+                                     (X[d][0] * gI[0][c] + X[d][1] * gI[1][c] + X[d][2] * gI[2][c] + X[d][3] * gI[3][c]);
+                    quad1 -= Gam(a1, d, c) * y;
+                    quad2 -= Gam(a2, d, c) * y;
+                }
+        }
+        pair_tail(A1C, BC, quad1);
+        pair_tail(A2C, BC, quad2);
+    };
+    switch (w) {   // pairs tt tx | xx xy | tx yy | yz zz | tz xz
+        case 0: wave_pairs(PairC<0>{}, PairC<0>{}, PairC<1>{}); break;
+        case 1: wave_pairs(PairC<1>{}, PairC<1>{}, PairC<2>{}); break;
+        case 2: wave_pairs(PairC<2>{}, PairC<0>{}, PairC<2>{}); break;
+        case 3: wave_pairs(PairC<3>{}, PairC<2>{}, PairC<3>{}); break;
+        default: wave_pairs(PairC<3>{}, PairC<0>{}, PairC<1>{}); break;
     }
 }
 
