@@ -53,6 +53,37 @@ def algorithmic_bytes(cls, n_r, n_th, n_ph, n_v, K):
     return per_fp * fp + extra
 
 
+KERNEL_SOURCES = {"d_r": "derivs.hip", "d_theta": "derivs.hip", "d_phi": "derivs.hip", "rhs_stage": "rhs.hip",
+                  "filter_decompose": "filter.hip", "filter_recompose": "filter.hip", "filter_theta": "filter.hip",
+                  "filter_phi_analysis": "derivs.hip", "filter_phi_synthesis": "derivs.hip"}
+
+
+def profiled_traffic(workload, cls):
+    """HBM bytes per launch of a kernel class from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, each scaled by the reading of a copy
+    kernel of known size), or None when there is none or the kernel's source
+    file has changed since the counters were taken (sha256 recorded there)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_%s.md" % workload)
+    if not os.path.exists(path):
+        return None
+    src = KERNEL_SOURCES[cls]
+    want, val = None, None
+    for line in open(path):
+        if line.startswith("source-sha256 %s " % src):
+            want = line.split()[2]
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) >= 6 and cells[0] == cls:
+            try:
+                val = float(cells[5])
+            except ValueError:
+                val = None
+    if want is None or val is None:
+        return None
+    have = hashlib.sha256(open(os.path.join(ROOT, "paper_1104_3408_amd", "csrc", src), "rb").read()).hexdigest()
+    return val if have == want else None
+
+
 def run_variant(shells, n_v, precision, steps, warmup, seed0):
     """Throughput of one workload: seeded perturbed Kerr-Schild data on every
     shell (seed0 + shell index), filtered RK4 steps with the step graph."""
@@ -199,7 +230,7 @@ def main():
         avg_s = kern[dom]["avg_us"] * 1e-6
         ach = byts / avg_s / 1e9
         out["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                           "frac": ach / HBM_PEAK_GBS, "traffic": profiled_traffic(args.workload, dom),
                            "bytes_per_launch": byts, "avg_launch_us": kern[dom]["avg_us"]}
         out["kernels"] = kern
         out["timing_pass_ms_per_step"] = 1e3 * (t3 - t2) / args.steps

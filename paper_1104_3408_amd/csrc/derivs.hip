@@ -33,6 +33,10 @@
 //            the Fourier analysis/synthesis matrices of the filter (Sec. 3.1).
 #include "internal.h"
 
+// Unroll factor of the contraction loops (lets the scalar loads of operator
+// rows run ahead of the FMAs; measured against 1, 2 and the default).
+#define SG_CONTRACT_UNROLL 4
+
 namespace sg {
 
 namespace {
@@ -67,6 +71,7 @@ __global__ __launch_bounds__(256) void k_dr(const double* __restrict__ in, doubl
     double acc[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[r] = 0.0;
+    #pragma unroll SG_CONTRACT_UNROLL
     for (int kk = 0; kk < n_r; ++kk) {
         const double v = sm[kk * kDrStride + lane];
         const double* d = Dw + kk * R;
@@ -129,6 +134,7 @@ __global__ __launch_bounds__(256) void k_dtheta(const double* __restrict__ in, O
     T aS[R], aA[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) aS[r] = aA[r] = (T)0;
+    #pragma unroll SG_CONTRACT_UNROLL
     for (int ip = 0; ip < n_th; ++ip) {
         const T sv = sS[ip * 64 + lane], av = sA[ip * 64 + lane];
         const T* hs = Sw + ip * R;
@@ -212,6 +218,7 @@ __global__ __launch_bounds__(256) void k_axis(const double* __restrict__ in, O* 
         T acc[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) acc[r] = (T)0;
+        #pragma unroll SG_CONTRACT_UNROLL
         for (int ri = 0; ri < n_in; ++ri) {
             const T v = sm[ri * 64 + lane] - mt;   // mt = 0 for FP32 tiles
             const T* wr = Ww + ri * R;

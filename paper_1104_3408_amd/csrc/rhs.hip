@@ -29,23 +29,20 @@ struct PairC {
     static constexpr int value = Q;
 };
 
-// Waves per SIMD the register allocation must allow (2: 256 VGPRs, 3: 168).
-#ifndef SG_RHS_WAVES_PER_SIMD
-#define SG_RHS_WAVES_PER_SIMD 2
-#endif
-
 constexpr int kPts = 64;      // grid points per workgroup
-constexpr int kWaves = 5;     // wave w owns symmetric pairs 2w and 2w+1
+constexpr int kWaves = 4;     // waves per workgroup
 
-// Workgroup = 64 consecutive grid points (one per lane) x 5 waves.  The
-// points' variables are staged in LDS ([item][lane], conflict-free); every
-// wave recomputes the 3+1 quantities in registers, a few per-point vectors
-// shared by all pairs are formed once into LDS, and then wave w evaluates
-// everything that belongs to its two symmetric pairs ab: the sources and
-// derivative terms of d_t g_ab, d_t Pi_ab and d_t Phi_xab, the boundary
-// operator (which couples only fields of one pair) and the RK4 stage update.
+// Workgroup = 64 consecutive grid points (one per lane) x 4 waves; at 256
+// VGPRs and 56 KB of LDS two workgroups share a CU.  The points' variables
+// are staged in LDS ([item][lane], conflict-free); every wave recomputes the
+// 3+1 quantities in registers, a few per-point vectors shared by all pairs
+// are formed once into LDS, and then wave w evaluates everything that belongs
+// to its symmetric pairs ab (three pairs for waves 0 and 1, two for 2 and 3,
+// all sharing one index): the sources and derivative terms of d_t g_ab,
+// d_t Pi_ab and d_t Phi_xab, the boundary operator (which couples only fields
+// of one pair) and the RK4 stage update.
 template <int NV, typename TD>
-__global__ __launch_bounds__(kWaves * 64, SG_RHS_WAVES_PER_SIMD) void k_rhs(KShell s, const double* __restrict__ u,
+__global__ __launch_bounds__(kWaves * 64, 2) void k_rhs(KShell s, const double* __restrict__ u,
                                              const double* __restrict__ du, const TD* __restrict__ dang, int cart,
                                              double* __restrict__ out, const double* __restrict__ ubase,
                                              double* __restrict__ acc, double dt, int stage, long long blk) {
@@ -63,7 +60,6 @@ __global__ __launch_bounds__(kWaves * 64, SG_RHS_WAVES_PER_SIMD) void k_rhs(KShe
         s.dH += (long long)blockIdx.y * 12 * s.npts;
     }
     __shared__ double su[NV][kPts];          // state of the 64 points
-    __shared__ double sdu[3][NV][kPts];      // Cartesian first derivatives d_x u
     __shared__ double sH[4][kPts];           // H_a
     __shared__ double sdH[4][4][kPts];       // d_a H_b (a = t from the state or 0)
     __shared__ double sdtg[10][kPts];        // d_t g_ab, eq. gdot
@@ -86,39 +82,12 @@ __global__ __launch_bounds__(kWaves * 64, SG_RHS_WAVES_PER_SIMD) void k_rhs(KShe
     const int j = ok ? (int)(p / ((long long)s.n_r * s.n_th)) : 0;
     const double st = s.sth[i], ct = s.cth[i], sp = s.sph[j], cp = s.cph[j];
 
-    // ---- stage the variables and their derivatives in one burst; points past
-    // the end get Minkowski data and zero derivatives. Derivatives are turned
-    // into Cartesian ones here: chain rule of Sec. 2.2 (eq. dvdx) with the
-    // analytic Jacobian d(r, theta, phi)/d(x, y, z). ----------------------------
-    {
-        const double ir = ok ? 1.0 / s.rk[k] : 0.0, irs = ok ? ir / st : 0.0;
-        const double J[3][3] = {{st * cp, ct * cp * ir, -sp * irs},
-                                {st * sp, ct * sp * ir, cp * irs},
-                                {ct, -st * ir, 0.0}};
+    // ---- stage the variables; points past the end get Minkowski data --------
 #pragma unroll
-        for (int t = 0; t < (NV + kWaves - 1) / kWaves; ++t) {
-            const int f = w + t * kWaves;
-            if (f >= NV) break;
-            const long long q = (long long)f * np + p;
-            double v, d0 = 0.0, d1 = 0.0, d2 = 0.0;
-            if (ok) {
-                v = u[q];
-                d0 = du[q];
-                d1 = (double)dang[q];
-                d2 = (double)dang[blk + q];
-            } else {
-                v = (f == 0) ? -1.0 : ((f == 4 || f == 7 || f == 9) ? 1.0 : 0.0);
-            }
-            su[f][lane] = v;
-            if (cart) {
-                sdu[0][f][lane] = d0;
-                sdu[1][f][lane] = d1;
-                sdu[2][f][lane] = d2;
-            } else {
-#pragma unroll
-                for (int x = 0; x < 3; ++x) sdu[x][f][lane] = J[x][0] * d0 + J[x][1] * d1 + J[x][2] * d2;
-            }
-        }
+    for (int t = 0; t < (NV + kWaves - 1) / kWaves; ++t) {
+        const int f = w + t * kWaves;
+        if (f >= NV) break;
+        su[f][lane] = ok ? u[(long long)f * np + p] : ((f == 0) ? -1.0 : ((f == 4 || f == 7 || f == 9) ? 1.0 : 0.0));
     }
     if (NV == 50) {
         for (int e = threadIdx.x; e < 16 * kPts; e += kWaves * 64) {
@@ -162,7 +131,23 @@ __global__ __launch_bounds__(kWaves * 64, SG_RHS_WAVES_PER_SIMD) void k_rhs(KShe
     }
     const double nu[4] = {ial, -bu[0] * ial, -bu[1] * ial, -bu[2] * ial};
     const double nl0 = -al;   // n_a = (-alpha, 0, 0, 0)
-    auto CD = [&](int x, int mu) -> double { return sdu[x][mu][lane]; };   // d_x u_mu
+    // Cartesian derivatives d_x u_mu, x = 0..2, of this thread's point: chain
+    // rule of Sec. 2.2 (eq. dvdx) with the analytic Jacobian d(r, theta,
+    // phi)/d(x, y, z)
+    auto cartd = [&](int mu, double d[3]) {
+        d[0] = d[1] = d[2] = 0.0;
+        if (!ok) return;
+        const long long q = (long long)mu * np + p;
+        const double d0 = du[q], d1 = (double)dang[q], d2 = (double)dang[blk + q];
+        if (cart) {
+            d[0] = d0; d[1] = d1; d[2] = d2;
+        } else {
+            const double ir = 1.0 / s.rk[k], irs = ir / st;
+            d[0] = st * cp * d0 + ct * cp * ir * d1 - sp * irs * d2;
+            d[1] = st * sp * d0 + ct * sp * ir * d1 + cp * irs * d2;
+            d[2] = ct * d0 - st * ir * d1;
+        }
+    };
 
     // ---- shared per-point quantities, phase 1 --------------------------------
     if (w == 0) {
@@ -177,8 +162,10 @@ __global__ __launch_bounds__(kWaves * 64, SG_RHS_WAVES_PER_SIMD) void k_rhs(KShe
             for (int b = 0; b < 4; ++b) {
                 sH[b][lane] = su[50 + b][lane];
                 sdH[0][b][lane] = su[54 + b][lane];              // d_t H_b = Q_b
+                double d[3];
+                cartd(50 + b, d);
 #pragma unroll
-                for (int x = 0; x < 3; ++x) sdH[x + 1][b][lane] = CD(x, 50 + b);
+                for (int x = 0; x < 3; ++x) sdH[x + 1][b][lane] = d[x];
             }
         }
     } else if (w == 2) {
@@ -244,13 +231,10 @@ __global__ __launch_bounds__(kWaves * 64, SG_RHS_WAVES_PER_SIMD) void k_rhs(KShe
         constexpr int q = pr(a, b);
         // Cartesian derivatives of g_ab, Pi_ab, Phi_xab
         double dg[3], dP[3], dF[3][3];
+        cartd(q, dg);
+        cartd(10 + q, dP);
 #pragma unroll
-        for (int x = 0; x < 3; ++x) {
-            dg[x] = CD(x, q);
-            dP[x] = CD(x, 10 + q);
-#pragma unroll
-            for (int y = 0; y < 3; ++y) dF[y][x] = CD(x, 20 + 10 * y + q);
-        }
+        for (int y = 0; y < 3; ++y) cartd(20 + 10 * y + q, dF[y]);
         double nabH = 0.5 * (sdH[a][b][lane] + sdH[b][a][lane]);
 #pragma unroll
         for (int c = 0; c < 4; ++c) nabH -= sHu[c][lane] * Gam(c, a, b);
@@ -340,14 +324,16 @@ __global__ __launch_bounds__(kWaves * 64, SG_RHS_WAVES_PER_SIMD) void k_rhs(KShe
     // so the b-dependent contractions of the quadratic term are formed once;
     // all indices are compile-time constants in each instance of the body, so
     // every LDS offset and every branch on the indices folds away -------------
-    auto wave_pairs = [&](auto BC, auto A1C, auto A2C) {
+    auto wave_pairs = [&](auto BC, auto A1C, auto A2C, auto A3C) {
         constexpr int b = decltype(BC)::value, a1 = decltype(A1C)::value, a2 = decltype(A2C)::value;
+        constexpr int a3 = decltype(A3C)::value < 0 ? a2 : decltype(A3C)::value;   // < 0: no third pair
+        constexpr bool three = decltype(A3C)::value >= 0;
         // quadratic bracket of eq. Pidot for (a, b),
         //   g^cd (gamma^ij Phi_iac Phi_jbd - Pi_ac Pi_bd) - g^cd g^ef Gamma_ace Gamma_bdf
         //   = Phi_xac Z_xc - Pi_ac V_c - Gamma_ace Y^ce,
         // with Z_xc = g^cd gamma^xy Phi_ybd, V_c = g^cd Pi_bd and
         // Y = G Gamma_b G (Gamma_b the 4x4 matrix Gamma_bdf), all of row b.
-        double quad1 = 0.0, quad2 = 0.0;
+        double quad1 = 0.0, quad2 = 0.0, quad3 = 0.0;
         {
             double Pb[3][4], pb[4];
 #pragma unroll
@@ -366,6 +352,7 @@ __global__ __launch_bounds__(kWaves * 64, SG_RHS_WAVES_PER_SIMD) void k_rhs(KShe
                 const double vc = gI[c][0] * pb[0] + gI[c][1] * pb[1] + gI[c][2] * pb[2] + gI[c][3] * pb[3];
                 quad1 += PH(0, a1, c) * zc[0] + PH(1, a1, c) * zc[1] + PH(2, a1, c) * zc[2] - PI(a1, c) * vc;
                 quad2 += PH(0, a2, c) * zc[0] + PH(1, a2, c) * zc[1] + PH(2, a2, c) * zc[2] - PI(a2, c) * vc;
+                if (three) quad3 += PH(0, a3, c) * zc[0] + PH(1, a3, c) * zc[1] + PH(2, a3, c) * zc[2] - PI(a3, c) * vc;
             }
         }
         {
@@ -387,17 +374,26 @@ __global__ __launch_bounds__(kWaves * 64, SG_RHS_WAVES_PER_SIMD) void k_rhs(KShe
                                      (X[d][0] * gI[0][c] + X[d][1] * gI[1][c] + X[d][2] * gI[2][c] + X[d][3] * gI[3][c]);
                     quad1 -= Gam(a1, d, c) * y;
                     quad2 -= Gam(a2, d, c) * y;
+                    if (three) quad3 -= Gam(a3, d, c) * y;
                 }
         }
+        // the barriers keep each pair's derivative loads from being hoisted
+        // above the previous pair (register pressure)
+        __builtin_amdgcn_sched_barrier(0);
         pair_tail(A1C, BC, quad1);
+        __builtin_amdgcn_sched_barrier(0);
         pair_tail(A2C, BC, quad2);
+        if constexpr (three) {
+            __builtin_amdgcn_sched_barrier(0);
+            pair_tail(PairC<a3>{}, BC, quad3);
+        }
     };
-    switch (w) {   // pairs tt tx | xx xy | tx yy | yz zz | tz xz
-        case 0: wave_pairs(PairC<0>{}, PairC<0>{}, PairC<1>{}); break;
-        case 1: wave_pairs(PairC<1>{}, PairC<1>{}, PairC<2>{}); break;
-        case 2: wave_pairs(PairC<2>{}, PairC<0>{}, PairC<2>{}); break;
-        case 3: wave_pairs(PairC<3>{}, PairC<2>{}, PairC<3>{}); break;
-        default: wave_pairs(PairC<3>{}, PairC<0>{}, PairC<1>{}); break;
+    using None = PairC<-1>;
+    switch (w) {   // pairs tt tx ty | xx xy xz | yy yz | zz tz
+        case 0: wave_pairs(PairC<0>{}, PairC<0>{}, PairC<1>{}, PairC<2>{}); break;
+        case 1: wave_pairs(PairC<1>{}, PairC<1>{}, PairC<2>{}, PairC<3>{}); break;
+        case 2: wave_pairs(PairC<2>{}, PairC<2>{}, PairC<3>{}, None{}); break;
+        default: wave_pairs(PairC<3>{}, PairC<3>{}, PairC<0>{}, None{}); break;
     }
 }
 
