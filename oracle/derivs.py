@@ -33,21 +33,31 @@ def meridian_circle(u, j, shell):
 
 def d_theta(u, shell):
     """d/dtheta with the Fourier matrix on the double-covered theta circle,
-    keeping only the single-cover rows (Sec. 2.1, Sec. 2.4 eq. D2)."""
+    keeping only the single-cover rows (Sec. 2.1, Sec. 2.4 eq. D2).  As in
+    d_phi, the mean over each circle is subtracted first (same result up to
+    rounding)."""
     n_th = shell.n_theta
     FD = fourier_diff_matrix(2 * n_th)
     out = np.empty_like(u)
     for j in range(shell.n_phi):
         circle = meridian_circle(u, j, shell)
+        circle = circle - circle.mean(axis=-2, keepdims=True)   # FD annihilates constants
         dcircle = np.einsum('ab,...bk->...ak', FD, circle)
         out[..., j, :, :] = dcircle[..., :n_th, :]
     return out
 
 
 def d_phi(u, shell):
-    """d/dphi with the Fourier matrix on the N_phi-point circle (Sec. 2.4 eq. D3)."""
+    """d/dphi with the Fourier matrix on the N_phi-point circle (Sec. 2.4 eq. D3).
+
+    The mean over the circle is subtracted first.  The derivative of a
+    constant vanishes, so the rows of FD sum to zero (Sec. 2.3) and the result
+    is the same up to rounding; the rounding is then proportional to the
+    variation of u along the circle instead of to its size, which matters
+    where the chain rule divides by r sin(theta)."""
     FD = fourier_diff_matrix(shell.n_phi)
-    return np.einsum('jl,...lik->...jik', FD, u)
+    v = u - u.mean(axis=-3, keepdims=True)
+    return np.einsum('jl,...lik->...jik', FD, v)
 
 
 def coordinate_derivs(u, shell):
