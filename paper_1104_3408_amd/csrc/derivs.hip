@@ -93,20 +93,26 @@ __global__ __launch_bounds__(256) void k_dr(const double* __restrict__ in, doubl
 }
 
 // d_theta on meridian pairs.  Column c = (f * half + jp) * n_r + k; 64
-// columns per workgroup, wave w computes theta rows i = w R + r.
+// columns per workgroup, wave w computes theta rows i = w R + r.  The mean
+// of each meridian circle is removed first (the rows of the Fourier matrix
+// sum to zero), in FP64 before any rounding to T: S_i - (sum_i S_i)/N_theta.
+constexpr int kThMaxPerThread = 16;   // N_theta <= 64 rows over 4 waves
+
 template <int R, typename T, typename O>
 __global__ __launch_bounds__(256) void k_dtheta(const double* __restrict__ in, O* __restrict__ out,
                                                 const T* __restrict__ Hsb, const T* __restrict__ Hab,
                                                 int n_r, int n_th, int n_ph, long long n_cols) {
-    extern __shared__ double smd[];  // S [n_th][64], A [n_th][64] in T
+    extern __shared__ double smd[];  // S [n_th][64], A [n_th][64] in T, then partial sums [4][64] in FP64
     T* sm = reinterpret_cast<T*>(smd);
     T* sS = sm;
     T* sA = sm + n_th * 64;
+    double* spart = reinterpret_cast<double*>(sm + 2 * n_th * 64);
     const int half = n_ph / 2;
     const long long plane = (long long)n_th * n_r;
     const long long c0 = (long long)blockIdx.x * 64;
-    // this thread's column (fixed: the loop steps by a multiple of 64)
+    // this thread's column; it loads rows ip = w, w + 4, ...
     const int lane = threadIdx.x & 63;
+    const int w = wave_id();
     const long long c = c0 + lane;
     const bool cok = c < n_cols;
     long long f = 0;
@@ -118,17 +124,50 @@ __global__ __launch_bounds__(256) void k_dtheta(const double* __restrict__ in, O
         jp = (int)(fj - f * half);
     }
     const double* base = in + f * n_ph * plane + (long long)jp * plane + k;
-    for (int ip = threadIdx.x >> 6; ip < n_th; ip += 4) {
-        double a = 0.0, b = 0.0;
-        if (cok) {
-            a = base[(long long)ip * n_r];
-            b = base[half * plane + (long long)ip * n_r];
+    double ms = 0.0;   // circle mean of S (subtracted per lane for FP64 tiles)
+    if (sizeof(T) == 8) {
+        double part = 0.0;
+        for (int ip = w; ip < n_th; ip += 4) {
+            double a = 0.0, b = 0.0;
+            if (cok) {
+                a = base[(long long)ip * n_r];
+                b = base[half * plane + (long long)ip * n_r];
+            }
+            part += a + b;
+            sS[ip * 64 + lane] = (T)(a + b);
+            sA[ip * 64 + lane] = (T)(a - b);
         }
-        sS[ip * 64 + lane] = (T)(a + b);
-        sA[ip * 64 + lane] = (T)(a - b);
+        spart[w * 64 + lane] = part;
+        __syncthreads();
+        ms = (spart[lane] + spart[64 + lane] + spart[128 + lane] + spart[192 + lane]) / n_th;
+    } else {
+        double sv[kThMaxPerThread], av[kThMaxPerThread];
+        double part = 0.0;
+#pragma unroll
+        for (int t = 0; t < kThMaxPerThread; ++t) {
+            const int ip = w + 4 * t;
+            double a = 0.0, b = 0.0;
+            if (cok && ip < n_th) {
+                a = base[(long long)ip * n_r];
+                b = base[half * plane + (long long)ip * n_r];
+            }
+            sv[t] = a + b;
+            av[t] = a - b;
+            part += sv[t];
+        }
+        spart[w * 64 + lane] = part;
+        __syncthreads();
+        const double mc = (spart[lane] + spart[64 + lane] + spart[128 + lane] + spart[192 + lane]) / n_th;
+#pragma unroll
+        for (int t = 0; t < kThMaxPerThread; ++t) {
+            const int ip = w + 4 * t;
+            if (ip < n_th) {
+                sS[ip * 64 + lane] = (T)(sv[t] - mc);
+                sA[ip * 64 + lane] = (T)av[t];
+            }
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    const int w = wave_id();
     const T* Sw = Hsb + (long long)w * n_th * R;
     const T* Aw = Hab + (long long)w * n_th * R;
     T aS[R], aA[R];
@@ -136,7 +175,7 @@ __global__ __launch_bounds__(256) void k_dtheta(const double* __restrict__ in, O
     for (int r = 0; r < R; ++r) aS[r] = aA[r] = (T)0;
     #pragma unroll SG_CONTRACT_UNROLL
     for (int ip = 0; ip < n_th; ++ip) {
-        const T sv = sS[ip * 64 + lane], av = sA[ip * 64 + lane];
+        const T sv = sS[ip * 64 + lane] - (T)ms, av = sA[ip * 64 + lane];   // ms = 0 for FP32 tiles
         const T* hs = Sw + ip * R;
         const T* ha = Aw + ip * R;
 #pragma unroll
@@ -297,7 +336,8 @@ static hipError_t dtheta_t(const KShell& s, const double* in, O* out, const T* H
                            hipStream_t st) {
     const long long n_cols = (long long)n_fields * (s.n_ph / 2) * s.n_r;
     const unsigned blocks = (unsigned)((n_cols + 63) / 64);
-    const size_t shm = sizeof(T) * 2 * size_t(s.n_th) * 64;
+    if (s.n_th > 4 * kThMaxPerThread) return hipErrorInvalidValue;
+    const size_t shm = sizeof(T) * 2 * size_t(s.n_th) * 64 + 4 * 64 * sizeof(double);
     switch (s.Hth_R) {
 #define X(R) case R: hipLaunchKernelGGL((k_dtheta<R, T, O>), dim3(blocks), dim3(256), shm, st, in, out, Hsb, Hab, s.n_r, s.n_th, s.n_ph, n_cols); break;
         SG_R_CASES(X)

@@ -1,0 +1,177 @@
+"""GPU parity at the full sizes of the batched workloads, in the launch
+configuration bench.py times (one grid holding every shell, FP64, Yn filter
+n_f = 4, Courant factor 4, the captured step graph), checked against the
+oracle on sampled shells, sampled points and sampled radii.
+
+* 64 shells of four sizes (16 each of 17x16x32 ... 49x48x96): one filtered
+  RK4 step of the whole batch; the first and last shells of the runs and one
+  inside are compared with the oracle's step in full.
+* 8 shells of 65x64x128 with 58 fields: initial data and spectral derivatives
+  of one shell against the oracle in full, the right-hand side at sampled
+  points (all boundary points of a meridian plane among them), the filter on
+  sampled radii (the filter acts on each sphere separately), and one rk_step
+  of the whole batch against the same step composed from those checked entry
+  points (the oracle's step at this size takes minutes).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_1104_3408_amd import shellspec as ss
+from paper_1104_3408_amd import inputs
+from oracle.grid import Shell
+from oracle import derivs as od
+from oracle import ghg
+from oracle import initial_data as oid
+from oracle import tensor_filter as otf
+from oracle.evolve import Evolution
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    ss.lib()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b, scale=None):
+    s = np.abs(b).max() if scale is None else scale
+    return np.abs(a - b).max() / max(s, 1e-300)
+
+
+def _grid(name):
+    shells, n_v = inputs.workload_shells(name)
+    g = ss.ShellGrid(shells, n_fields=n_v, filter="Yn", n_f=4, courant=4.0)
+    return g, shells, n_v, inputs.WORKLOAD_SEED[name]
+
+
+def test_batch64_step_on_sampled_shells():
+    g, shells, n_v, seed0 = _grid("batch64")
+    g10 = []
+    for k in range(len(shells)):
+        r, th, ph = g.coords(k)
+        g10.append(inputs.perturbed_kerr_schild(seed0 + k, r, th, ph))
+    ut = torch.zeros(g.state_size, dtype=torch.float64, device="cuda")
+    g.kerr_schild_data(dev(np.concatenate([x.ravel() for x in g10])), ut)
+    u0 = host(ut)
+    g.rk_step(ut, 1)
+    got = host(ut)
+    for k in (0, 23, 47, 48, 63):
+        sh = Shell(*shells[k])
+        off, cnt, dt = g.info(k)
+        u_ref = oid.first_order_data(g10[k], sh)
+        H, dH = oid.static_gauge(u_ref, sh)
+        assert rel(u0[off:off + cnt].reshape(u_ref.shape), u_ref) < TOL, k
+        ref = Evolution(sh, n_v, H, dH, "Yn", 4).rk4_step(u_ref, dt)
+        mine = got[off:off + cnt].reshape(ref.shape)
+        print("batch64 shell %d %s: step rel err %.2e" % (k, shells[k][:3], rel(mine, ref)), flush=True)
+        assert rel(mine, ref) < TOL, k
+        # the step changes the state by 1e-8..1e-6 of its size; the change
+        # itself agrees to four digits
+        chg = np.abs(ref - u_ref).max() / np.abs(u_ref).max()
+        assert chg > 1e3 * TOL and rel(mine - u_ref, ref - u_ref) < 1e-4, (k, chg)
+
+
+def test_large8_entry_points_and_step():
+    g, shells, n_v, seed0 = _grid("large8")
+    assert n_v == 58
+    g10, extra = [], []
+    for k in range(len(shells)):
+        r, th, ph = g.coords(k)
+        g10.append(inputs.perturbed_kerr_schild(seed0 + k, r, th, ph))
+        extra.append(np.concatenate(inputs.gauge_perturbation(seed0 + 1000 + k, r, th, ph)))
+    u0 = torch.zeros(g.state_size, dtype=torch.float64, device="cuda")
+    g.kerr_schild_data(dev(np.concatenate([x.ravel() for x in g10])), u0,
+                       extra8=dev(np.concatenate([x.ravel() for x in extra])))
+    ks = 3                                     # sampled shell
+    sh = Shell(*shells[ks])
+    off, cnt, dt = g.info(ks)
+    shape = (n_v,) + sh.shape
+
+    def shell_of(t):
+        return host(t[off:off + cnt]).reshape(shape)
+
+    # initial data (App. A.3 with the seeded gauge fields)
+    u50 = oid.first_order_data(g10[ks], sh)
+    H0, _ = oid.static_gauge(u50, sh)
+    dHp, Q = np.split(extra[ks], 2)
+    u_ref = np.concatenate([u50, H0 + dHp, Q])
+    got0 = shell_of(u0)
+    err = np.abs(got0 - u_ref) / np.abs(u_ref).max()
+    worst = np.unravel_index(np.argmax(err), err.shape)
+    print("large8 initial data: max rel err %.2e at (mu, j, i, k) = %s; by group g %.1e Pi %.1e Phi %.1e H %.1e "
+          "Q %.1e" % (err.max(), worst, err[:10].max(), err[10:20].max(), err[20:50].max(), err[50:54].max(),
+                      err[54:].max()), flush=True)
+    assert err.max() < TOL
+    u_ref = shell_of(u0)                       # identical inputs from here on
+
+    # Cartesian spectral derivatives of the whole batch
+    du = torch.zeros(3 * g.state_size, dtype=torch.float64, device="cuda")
+    g.spec_derivs(u0, du, ss.SG_CART)
+    du_ref = np.array(od.cartesian_derivs(u_ref, sh))
+    blk = 3 * off
+    got_du = host(du[blk:blk + 3 * cnt]).reshape((3,) + shape)
+    for x in range(3):
+        assert rel(got_du[x], du_ref[x]) < TOL, x
+
+    # right-hand side with the boundary operator at sampled points
+    rt = torch.zeros_like(u0)
+    g.ghg_rhs(u0, rt)
+    got_r = shell_of(rt)
+    rng = np.random.default_rng(7)
+    n_ph, n_th, n_r = sh.shape
+    pts = [(int(rng.integers(n_ph)), int(rng.integers(n_th)), int(rng.integers(n_r))) for _ in range(2000)]
+    pts += [(5, i, n_r - 1) for i in range(n_th)]          # outer boundary, one meridian
+    idx = tuple(np.array(pts).T)
+    up = u_ref[(slice(None),) + idx]
+    dup = du_ref[(slice(None), slice(None)) + idx]
+    r_ref = ghg.rhs(up, dup)
+    src = ghg.rhs(up, 0 * dup)
+    x, y, z = sh.cartesian()
+    rad = np.sqrt(x * x + y * y + z * z)
+    xhat = np.array([x, y, z])[(slice(None),) + idx] / rad[idx]
+    bnd = np.array([p[2] == n_r - 1 for p in pts])
+    r_ref[:, bnd] = ghg.freeze_incoming(r_ref[:, bnd], up[:, bnd], xhat[:, bnd])
+    scale = max(np.abs(src).max(), np.abs(r_ref - src).max())
+    assert rel(got_r[(slice(None),) + idx], r_ref, scale) < TOL
+
+    # tensor filter on sampled radii (each sphere is filtered on its own)
+    uf = u0.clone()
+    g.swsh_filter(uf)
+    got_f = shell_of(uf)
+    radii = [0, 31, n_r - 1]
+    sub = Shell(len(radii), n_th, n_ph, sh.r_min, sh.r_max)
+    f_ref = otf.yn_filter(u_ref[..., radii], sub, 4)
+    assert rel(got_f[..., radii], f_ref) < TOL
+
+    # one captured rk_step of the batch against the step composed from the
+    # checked entry points (classical RK4, then the filter)
+    def k_of(v):
+        out = torch.zeros_like(v)
+        g.ghg_rhs(v, out)
+        return out
+    k1 = k_of(u0)
+    k2 = k_of(u0 + 0.5 * dt * k1)
+    k3 = k_of(u0 + 0.5 * dt * k2)
+    k4 = k_of(u0 + dt * k3)
+    comp = u0 + (dt / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+    g.swsh_filter(comp)
+    ut = u0.clone()
+    g.rk_step(ut, 1)
+    scale = float(u0.abs().max())
+    err = float((ut - comp).abs().max()) / scale
+    chg = float((comp - u0).abs().max()) / scale
+    print("large8 step vs composed step: %.2e (change of the state %.2e)" % (err, chg), flush=True)
+    assert err < TOL and chg > 1e-9
