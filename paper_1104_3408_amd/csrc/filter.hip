@@ -21,9 +21,6 @@
 //   H_a, Q_a (4 each, 58 fields): t r real, m (n=1) complex.
 #include "internal.h"
 
-// Unroll factor of the contraction loops (lets the scalar loads of operator
-// rows run ahead of the FMAs; measured against 1, 2 and the default).
-#define SG_CONTRACT_UNROLL 4
 
 namespace sg {
 
@@ -321,7 +318,7 @@ __global__ __launch_bounds__(256) void k_ftheta(int n_r, int n_th, int m_keep, i
         double acc0[R], acc1[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) acc0[r] = acc1[r] = 0.0;
-        #pragma unroll SG_CONTRACT_UNROLL
+        #pragma unroll 4   // operator loads run ahead of the FMAs (measured against 1, 2, default)
         for (int ip = 0; ip < n_th; ++ip) {
             const double a = v0[ip * 64 + lane], b = v1[ip * 64 + lane];
             const double* f = Fw + ip * R;
