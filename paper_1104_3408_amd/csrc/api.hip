@@ -143,26 +143,48 @@ size_t layout_offset(const sg_grid* g, int shell, int nfield) {
     return o;
 }
 
+// The three derivative contractions are independent: with fork (graph
+// capture only) d_theta and d_phi run on the two side streams beside d_r and
+// the stream waits for both, so the captured graph holds three parallel nodes.
+static hipError_t fork_begin(sg_grid* g, hipStream_t st) {
+    hipError_t e;
+    if ((e = hipEventRecord(g->fork_ev[0], st)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(g->side[0], g->fork_ev[0], 0)) != hipSuccess) return e;
+    return hipStreamWaitEvent(g->side[1], g->fork_ev[0], 0);
+}
+
+static hipError_t fork_end(sg_grid* g, hipStream_t st) {
+    hipError_t e;
+    if ((e = hipEventRecord(g->fork_ev[1], g->side[0])) != hipSuccess) return e;
+    if ((e = hipEventRecord(g->fork_ev[2], g->side[1])) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(st, g->fork_ev[1], 0)) != hipSuccess) return e;
+    return hipStreamWaitEvent(st, g->fork_ev[2], 0);
+}
+
 // Coordinate (or Cartesian) derivatives of n_fields variables of one shell.
-hipError_t derivs_shell(sg_grid* g, int s, const double* in, double* out, int nfield, bool cart, hipStream_t st) {
+hipError_t derivs_shell(sg_grid* g, int s, const double* in, double* out, int nfield, bool cart, hipStream_t st,
+                        bool fork = false) {
     const ShellHost& S = g->sh[s];
     const KShell v = S.view(nfield);
     const long long cnt = (long long)S.npts * nfield;
     hipError_t e;
+    if (fork && (e = fork_begin(g, st)) != hipSuccess) return e;
+    const hipStream_t s1 = fork ? g->side[0] : st, s2 = fork ? g->side[1] : st;
     {
         TimeScope ts(g, SG_K_DR, st);
         if ((e = launch_dr(v, in, out, nfield, st)) != hipSuccess) return e;
     }
     {
-        TimeScope ts(g, SG_K_DTHETA, st);
-        if ((e = launch_dtheta(v, in, out + cnt, nfield, st)) != hipSuccess) return e;
+        TimeScope ts(g, SG_K_DTHETA, s1);
+        if ((e = launch_dtheta(v, in, out + cnt, nfield, s1)) != hipSuccess) return e;
     }
     {
-        TimeScope ts(g, SG_K_DPHI, st);
-        if ((e = launch_axis(S.dph, in, out + 2 * cnt, (long long)S.d.n_theta * S.d.n_r, nfield, 1, st)) !=
+        TimeScope ts(g, SG_K_DPHI, s2);
+        if ((e = launch_axis(S.dph, in, out + 2 * cnt, (long long)S.d.n_theta * S.d.n_r, nfield, 1, s2)) !=
             hipSuccess)
             return e;
     }
+    if (fork && (e = fork_end(g, st)) != hipSuccess) return e;
     if (cart) return launch_chain(v, out, nfield, st);
     return hipSuccess;
 }
@@ -170,25 +192,28 @@ hipError_t derivs_shell(sg_grid* g, int s, const double* in, double* out, int nf
 // Mixed precision: d_r in FP64 into dr; d_theta, d_phi in FP32 into dang
 // (two blocks of n_fields * npts floats).
 hipError_t derivs_shell_mixed(sg_grid* g, int s, const double* in, double* dr, float* dang, int nfield,
-                              hipStream_t st) {
+                              hipStream_t st, bool fork = false) {
     const ShellHost& S = g->sh[s];
     const KShell v = S.view(nfield);
     const long long cnt = (long long)S.npts * nfield;
     hipError_t e;
+    if (fork && (e = fork_begin(g, st)) != hipSuccess) return e;
+    const hipStream_t s1 = fork ? g->side[0] : st, s2 = fork ? g->side[1] : st;
     {
         TimeScope ts(g, SG_K_DR, st);
         if ((e = launch_dr(v, in, dr, nfield, st)) != hipSuccess) return e;
     }
     {
-        TimeScope ts(g, SG_K_DTHETA, st);
-        if ((e = launch_dtheta_f32(v, in, dang, nfield, st)) != hipSuccess) return e;
+        TimeScope ts(g, SG_K_DTHETA, s1);
+        if ((e = launch_dtheta_f32(v, in, dang, nfield, s1)) != hipSuccess) return e;
     }
     {
-        TimeScope ts(g, SG_K_DPHI, st);
-        if ((e = launch_axis_f32(S.dph, in, dang + cnt, (long long)S.d.n_theta * S.d.n_r, nfield, 1, st)) !=
+        TimeScope ts(g, SG_K_DPHI, s2);
+        if ((e = launch_axis_f32(S.dph, in, dang + cnt, (long long)S.d.n_theta * S.d.n_r, nfield, 1, s2)) !=
             hipSuccess)
             return e;
     }
+    if (fork && (e = fork_end(g, st)) != hipSuccess) return e;
     return hipSuccess;
 }
 
@@ -442,6 +467,10 @@ void shell_grid_destroy(sg_grid* g) {
     if (!g) return;
     drop_graph(g);
     if (g->cap) (void)hipStreamDestroy(g->cap);
+    for (auto sd : g->side)
+        if (sd) (void)hipStreamDestroy(sd);
+    for (auto ev : g->fork_ev)
+        if (ev) (void)hipEventDestroy(ev);
     for (auto& s : g->sh) free_shell(s);
     for (void* p : {(void*)g->us, (void*)g->acc, (void*)g->dbuf, (void*)g->tcol, (void*)g->spec, (void*)g->spec2,
                     (void*)g->d_flag, (void*)g->d_groups, (void*)g->d_fsets, (void*)g->Hall, (void*)g->dHall})
@@ -528,7 +557,7 @@ sg_status ghg_rhs(sg_grid* g, const double* u, const double* du_cart, double* rh
 
 // One filtered RK4 step of every shell (Sec. 2.5): stage inputs u -> a -> b -> a,
 // the fourth stage writes u; then the filter.
-static hipError_t step_launches(sg_grid* g, double* u, const double* dt, hipStream_t st) {
+static hipError_t step_launches(sg_grid* g, double* u, const double* dt, hipStream_t st, bool fork) {
     const int nv = g->opt.n_fields;
     double* usA = g->us;
     double* usB = g->us + g->total;
@@ -548,14 +577,15 @@ static hipError_t step_launches(sg_grid* g, double* u, const double* dt, hipStre
         float* dang = reinterpret_cast<float*>(g->dbuf + S.count * R.count);
         for (int stage = 1; stage <= 4; ++stage) {
             if (mixed) {
-                if ((e = derivs_shell_mixed(g, R.first, in[stage - 1], g->dbuf, dang, nvr, st)) != hipSuccess)
+                if ((e = derivs_shell_mixed(g, R.first, in[stage - 1], g->dbuf, dang, nvr, st, fork)) != hipSuccess)
                     return e;
                 TimeScope ts(g, SG_K_RHS, st);
                 if ((e = launch_rhs_mixed(v, R.count, in[stage - 1], g->dbuf, dang, outp[stage - 1], u0, ac, h,
                                           stage, st)) != hipSuccess)
                     return e;
             } else {
-                if ((e = derivs_shell(g, R.first, in[stage - 1], g->dbuf, nvr, false, st)) != hipSuccess) return e;
+                if ((e = derivs_shell(g, R.first, in[stage - 1], g->dbuf, nvr, false, st, fork)) != hipSuccess)
+                    return e;
                 TimeScope ts(g, SG_K_RHS, st);
                 if ((e = launch_rhs(v, R.count, in[stage - 1], g->dbuf, false, outp[stage - 1], u0, ac, h, stage,
                                     st)) != hipSuccess)
@@ -578,8 +608,12 @@ static void drop_graph(sg_grid* g) {
 static sg_status capture_step(sg_grid* g, double* u, const std::vector<double>& dts) {
     drop_graph(g);
     if (!g->cap) HIP_TRY(hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking));
+    for (auto& sd : g->side)
+        if (!sd) HIP_TRY(hipStreamCreateWithFlags(&sd, hipStreamNonBlocking));
+    for (auto& ev : g->fork_ev)
+        if (!ev) HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     HIP_TRY(hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal));
-    const hipError_t e = step_launches(g, u, dts.data(), g->cap);
+    const hipError_t e = step_launches(g, u, dts.data(), g->cap, true);
     hipGraph_t graph = nullptr;
     const hipError_t e2 = hipStreamEndCapture(g->cap, &graph);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -618,7 +652,7 @@ sg_status rk_step(sg_grid* g, double* u, const double* dt, int n_steps, sg_strea
         }
         for (int n = 0; n < n_steps; ++n) HIP_TRY(hipGraphLaunch(g->sgraph.exec, st));
     } else {
-        for (int n = 0; n < n_steps; ++n) HIP_TRY(step_launches(g, u, dts.data(), st));
+        for (int n = 0; n < n_steps; ++n) HIP_TRY(step_launches(g, u, dts.data(), st, false));
     }
     if (g->opt.flags & SG_CHECK_FINITE) {
         HIP_TRY(hipMemsetAsync(g->d_flag, 0, sizeof(int), st));

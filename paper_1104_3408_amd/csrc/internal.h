@@ -118,6 +118,8 @@ struct sg_grid {
     int* d_flag = nullptr;
     sg::Timing tm;
     hipStream_t cap = nullptr;        // capture stream for the step graph
+    hipStream_t side[2] = {nullptr, nullptr};   // forked branches of the captured step
+    hipEvent_t fork_ev[3] = {nullptr, nullptr, nullptr};
     sg::StepGraph sgraph;
 };
 
