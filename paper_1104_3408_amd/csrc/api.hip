@@ -391,6 +391,9 @@ sg_status shell_grid_create(const sg_shell_desc* shells, int n_shells, const sg_
             }
         int passes = 0;
         blocked_shape(nr, H.Dr_R, passes);
+        int passes_th = 0;
+        blocked_shape(nt, H.Hth_R, passes_th);
+        if (passes != 1 || passes_th != 1) return cleanup(SG_ESHAPE, "radial or theta operator needs more than one pass");
         std::vector<double> Drb = block_operator(cheb_matrix(nr, H.d.r_min, H.d.r_max), nr, nr, H.Dr_R, 1);
         blocked_shape(nt, H.Hth_R, passes);
         std::vector<double> Hsb = block_operator(Hs, nt, nt, H.Hth_R, 1), Hab = block_operator(Ha, nt, nt, H.Hth_R, 1);

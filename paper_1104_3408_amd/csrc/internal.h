@@ -55,7 +55,7 @@ struct AxisOp {
 };
 
 // Largest number of output rows one wave accumulates per pass.
-constexpr int kMaxRows = 20;
+constexpr int kMaxRows = 20;   // one pass covers N_r <= 80 and N_theta <= 64 (k_dr, k_dtheta have no passes)
 
 struct ShellHost {
     sg_shell_desc d;
