@@ -118,6 +118,54 @@ def run_variant(shells, n_v, precision, steps, warmup, seed0):
     return res, u, g
 
 
+def fft_vs_matmul(reps=20):
+    """d_phi by the library's Fourier-matrix contraction against an FFT route
+    (torch.fft on ROCm: real FFT along phi, multiply by i m with the Nyquist
+    mode dropped, inverse FFT) on the same [field][phi][theta][r] layout, for
+    33 x N_theta x 2 N_theta shells with 50 fields.  Microseconds per call,
+    and the largest difference between the two results relative to max|d_phi u|."""
+    import torch
+    from paper_1104_3408_amd import shellspec as ss
+    rows = []
+    for n_th in (4, 8, 16, 24, 32, 48, 64):
+        n_ph, n_r = 2 * n_th, 33
+        g = ss.ShellGrid([(n_r, n_th, n_ph, 1.8, 11.8)])
+        gen = torch.Generator(device="cuda").manual_seed(n_th)
+        u = torch.randn(g.state_size, dtype=torch.float64, device="cuda", generator=gen)
+        du = torch.empty(3 * g.state_size, dtype=torch.float64, device="cuda")
+        g.spec_derivs(u, du)
+        g.enable_timing(True)
+        for _ in range(reps):
+            g.spec_derivs(u, du)
+        torch.cuda.synchronize()
+        ms, cnt = g.kernel_times()
+        g.enable_timing(False)
+        k = ss.KERNEL_CLASSES.index("d_phi")
+        mm_us = 1e3 * ms[k] / max(cnt[k], 1)
+        v = u.view(50, n_ph, n_th * n_r)
+        mult = 1j * torch.arange(n_ph // 2 + 1, device="cuda", dtype=torch.float64)
+        mult[-1] = 0.0                                     # Nyquist mode carries no derivative
+        mult = mult.view(1, -1, 1)
+
+        def fft_dphi():
+            return torch.fft.irfft(torch.fft.rfft(v, dim=1) * mult, n=n_ph, dim=1)
+
+        out = fft_dphi()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            out = fft_dphi()
+        e1.record()
+        torch.cuda.synchronize()
+        fft_us = 1e3 * e0.elapsed_time(e1) / reps
+        ref = du[2 * g.state_size:].view(50, n_ph, n_th * n_r)
+        diff = float((out - ref).abs().max() / ref.abs().max())
+        rows.append({"n_phi": n_ph, "matmul_us": round(mm_us, 2), "fft_us": round(fft_us, 2),
+                     "fft_over_matmul": round(fft_us / mm_us, 2), "max_rel_diff": diff})
+        del g, u, du, out
+    return rows
+
+
 def cpu_baseline(shell, g10, dt, gpu_state_after_one_step):
     """Oracle (numpy FP64) on one filtered RK4 step of the same workload."""
     import numpy as np
@@ -269,6 +317,8 @@ def main():
             var[name] = {"shells": len(bshells), "n_fields": bnv, "fp64": r64, "mixed_fp32_angular": r32}
             del u32, g32, u64h
             torch.cuda.empty_cache()
+        var["fft_vs_matmul_dphi"] = fft_vs_matmul()
+        log("FFT comparison done")
         out["variants"] = var
     if not args.no_cpu_baseline and len(shells) == 1:
         log("oracle step on the host")
