@@ -137,6 +137,31 @@ def rhs(u, du, H=None, dH=None):
     return pack(gdot, Pidot, Phidot, extra_dot)
 
 
+def constraints(u, du, H=None):
+    """Constraint fields of the first-order GHG system (App. A.1): the gauge
+    constraint C_a = H_a + Gamma_a and the first-order constraint
+    C_iab = d_i g_ab - Phi_iab.
+
+    u: state [n_v, ...]; du: Cartesian derivatives [3, n_v, ...] (only the
+    g_ab rows are used); H: gauge source [4, ...] for 50 fields (58 fields take
+    H_a from the state).  Returns (C_a [4, ...], C_iab [3, 10, ...]) with the
+    symmetric pairs in storage order."""
+    g, Pi, Phi, _ = unpack(u)
+    if u.shape[0] == 58:
+        H = u[50:54]
+    Gc = dependent(g, Pi, Phi)['Gam_c']
+    C_a = H + Gc
+    C_iab = du[:, 0:10] - u[20:50].reshape((3, 10) + u.shape[1:])
+    return C_a, C_iab
+
+
+def constraint_norms(C_a, C_iab):
+    """(max |C_a|, rms C_a, max |C_iab|, rms C_iab); rms over every component
+    and grid point."""
+    return (float(np.abs(C_a).max()), float(np.sqrt(np.mean(C_a ** 2))),
+            float(np.abs(C_iab).max()), float(np.sqrt(np.mean(C_iab ** 2))))
+
+
 def boundary_normal(u, xhat):
     """Outward unit normal of a sphere, s_i = xhat_i / sqrt(gamma^jk xhat_j xhat_k)
     and s^i = gamma^ij s_j (App. A.2 / A.3)."""

@@ -277,3 +277,49 @@ def test_short_evolution_stays_near_static():
         u = ev.rk4_step(u, courant_dt(sh))
     assert np.abs(u - u0).max() < 1e-2
     assert np.all(np.isfinite(u))
+
+
+def test_constraint_fields_vanish_for_exact_kerr_schild():
+    """C_a = H_a + Gamma_a and C_iab = d_i g_ab - Phi_iab (App. A.1) are zero
+    for the Kerr-Schild state with closed-form Phi, H_a = -Gamma_a from the
+    independent closed form, and d_i g from the complex step."""
+    x = _points(12, 5)
+    u = _ks_state(x)
+    du = np.zeros((3,) + u.shape)
+    du[:, 0:10] = _cstep(lambda xc: _ks_state(xc)[0:10], x)
+    C_a, C_iab = ghg.constraints(u, du, _ks_gauge(x))
+    assert np.abs(C_a).max() < 1e-14
+    assert np.abs(C_iab).max() < 1e-14
+
+
+def test_constraint_fields_report_planted_violations():
+    """A planted change of Phi_iab shows up as -delta in C_iab, of H_a as
+    +h in C_a; the 58-field state supplies H_a itself."""
+    rng = np.random.default_rng(9)
+    x = _points(10, 6)
+    u = _ks_state(x)
+    du = np.zeros((3,) + u.shape)
+    du[:, 0:10] = _cstep(lambda xc: _ks_state(xc)[0:10], x)
+    H = _ks_gauge(x)
+    delta = 1e-3 * rng.standard_normal((30, x.shape[1]))
+    h = 1e-3 * rng.standard_normal((4, x.shape[1]))
+    up = u.copy()
+    up[20:50] += delta
+    C_a, C_iab = ghg.constraints(up, du, H + h)
+    assert np.abs(C_iab + delta.reshape(3, 10, -1)).max() < 1e-14
+    # the Phi change also moves Gamma_a; the H change enters one to one
+    C_a0, _ = ghg.constraints(up, du, H)
+    assert np.abs(C_a - C_a0 - h).max() < 1e-15
+    u58 = np.concatenate([u, H + h, np.zeros_like(H)])
+    du58 = np.concatenate([du, np.zeros((3, 8) + u.shape[1:])], axis=1)
+    C58, _ = ghg.constraints(u58, du58)
+    assert np.abs(C58 - h).max() < 1e-14
+
+
+def test_constraint_norms_definition():
+    C_a = np.zeros((4, 5))
+    C_a[2, 3] = -2.0
+    C_iab = np.ones((3, 10, 5))
+    mx_a, rms_a, mx_i, rms_i = ghg.constraint_norms(C_a, C_iab)
+    assert (mx_a, mx_i, rms_i) == (2.0, 1.0, 1.0)
+    assert rms_a == pytest.approx(np.sqrt(4.0 / 20.0), rel=1e-15)
