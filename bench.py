@@ -104,6 +104,13 @@ def run_variant(shells, n_v, precision, steps, warmup, seed0):
     ex = torch.from_numpy(np.concatenate(extra)).cuda() if extra else None
     g.kerr_schild_data(torch.from_numpy(np.concatenate(g10)).cuda(), u, extra8=ex)
     del g10, extra, ex
+    norms = torch.zeros(4 * len(shells), dtype=torch.float64, device="cuda")
+
+    def constraint_norms():
+        """max over shells of (max |C_a|, rms C_a, max |C_iab|, rms C_iab)"""
+        g.ghg_constraints(u, norms)
+        return [float(x) for x in norms.view(-1, 4).max(dim=0).values.cpu()]
+    c0 = constraint_norms()
     g.rk_step(u, warmup)
     torch.cuda.synchronize()
     log("initial data and %d warmup steps done" % warmup)
@@ -114,7 +121,8 @@ def run_variant(shells, n_v, precision, steps, warmup, seed0):
     log("%d timed steps: %.3f ms/step" % (steps, 1e3 * (t1 - t0) / steps))
     fp = sum(n_v * a * b * c for (a, b, c, _, _) in shells)
     res = {"field_points": fp, "ms_per_step": 1e3 * (t1 - t0) / steps, "value": fp * steps / (t1 - t0),
-           "steps": steps, "state_finite": bool(torch.isfinite(u).all().item())}
+           "steps": steps, "state_finite": bool(torch.isfinite(u).all().item()),
+           "constraints_max_abs_rms_Ca_Ciab": {"initial": c0, "after_%d_steps" % (warmup + steps): constraint_norms()}}
     return res, u, g
 
 

@@ -132,6 +132,17 @@ sg_status spec_derivs(sg_grid* g, const double* u, double* du, int mode, sg_stre
  * Fourier synthesis (Sec. 3.1, eqs. Fanalysis/Fsynthesis, Nyquist dropped). */
 sg_status swsh_filter(sg_grid* g, double* u, sg_stream_t stream);
 
+/* Constraint monitor (App. A.1): per shell the gauge constraint
+ * C_a = H_a + Gamma_a (Gamma_a = g^bc Gamma_abc with d_t g from eq. gdot; H_a
+ * the static gauge for 50 fields, the state's H_a for 58) and the first-order
+ * constraint C_iab = d_i g_ab - Phi_iab, d_i g_ab the Cartesian spectral
+ * derivative of the state's g_ab.  u: device state (layout of rk_step).
+ * norms: caller-owned device array of 4 * n_shells doubles, per shell
+ * (max |C_a|, rms C_a, max |C_iab|, rms C_iab); rms over all components and
+ * grid points of the shell.  Stream-ordered; uses the grid's derivative
+ * workspace, so calls on one grid must not overlap.  SG_EINVAL on NULL. */
+sg_status ghg_constraints(sg_grid* g, const double* u, double* norms, sg_stream_t stream);
+
 /* Right-hand side d_t u of the first-order GHG system (App. A.1 eqs. gdot,
  * Phidot, Pidot with gamma_0 = gamma_2 = 1, gamma_1 = -1), with the
  * freezing-incoming boundary operator (App. A.3) applied on the outermost

@@ -426,6 +426,8 @@ sg_status shell_grid_create(const sg_shell_desc* shells, int n_shells, const sg_
         spec = std::max(spec, size_t(R.count) * g->n_cols * S.K * S.d.n_theta * S.d.n_r);
     }
     g->spec_size = spec;
+    size_t max_cblocks = 1;
+    for (const ShellHost& S : g->sh) max_cblocks = std::max(max_cblocks, (S.npts + 255) / 256);
     if (opt->n_fields == 50) {
         size_t pts = 0;
         for (auto& S : g->sh) pts += S.npts;
@@ -447,7 +449,8 @@ sg_status shell_grid_create(const sg_shell_desc* shells, int n_shells, const sg_
         hipMalloc((void**)&g->tcol, sizeof(double) * maxc) != hipSuccess ||
         hipMalloc((void**)&g->spec, sizeof(double) * spec) != hipSuccess ||
         hipMalloc((void**)&g->spec2, sizeof(double) * spec) != hipSuccess ||
-        hipMalloc((void**)&g->d_flag, sizeof(int)) != hipSuccess)
+        hipMalloc((void**)&g->d_flag, sizeof(int)) != hipSuccess ||
+        hipMalloc((void**)&g->cpart, sizeof(double) * 4 * max_cblocks) != hipSuccess)
         return cleanup(SG_ENOMEM, "workspace allocation failed");
     if (upload(&g->d_groups, g->groups) != hipSuccess || upload(&g->d_fsets, g->fsets) != hipSuccess)
         return cleanup(SG_ENOMEM, "group upload failed");
@@ -476,7 +479,8 @@ void shell_grid_destroy(sg_grid* g) {
         if (ev) (void)hipEventDestroy(ev);
     for (auto& s : g->sh) free_shell(s);
     for (void* p : {(void*)g->us, (void*)g->acc, (void*)g->dbuf, (void*)g->tcol, (void*)g->spec, (void*)g->spec2,
-                    (void*)g->d_flag, (void*)g->d_groups, (void*)g->d_fsets, (void*)g->Hall, (void*)g->dHall})
+                    (void*)g->d_flag, (void*)g->d_groups, (void*)g->d_fsets, (void*)g->Hall, (void*)g->dHall,
+                    (void*)g->cpart})
         if (p) (void)hipFree(p);
     for (auto e : g->tm.ev) (void)hipEventDestroy(e);
     delete g;
@@ -540,6 +544,19 @@ sg_status swsh_filter(sg_grid* g, double* u, sg_stream_t stream) {
     if (g->opt.filter_kind == SG_FILTER_NONE) return SG_OK;
     hipStream_t st = (hipStream_t)stream;
     for (const Run& R : g->runs) HIP_TRY(filter_run(g, R, u + g->sh[R.first].off, st));
+    return SG_OK;
+}
+
+sg_status ghg_constraints(sg_grid* g, const double* u, double* norms, sg_stream_t stream) {
+    if (!g || !u || !norms) return fail(SG_EINVAL, "NULL argument");
+    hipStream_t st = (hipStream_t)stream;
+    for (int s = 0; s < (int)g->sh.size(); ++s) {
+        const ShellHost& S = g->sh[s];
+        const KShell v = S.view(g->opt.n_fields);
+        // Cartesian derivatives of the ten g_ab of this shell into the workspace
+        HIP_TRY(derivs_shell(g, s, u + S.off, g->dbuf, 10, true, st));
+        HIP_TRY(launch_constraints(v, u + S.off, g->dbuf, g->cpart, norms + 4 * s, st));
+    }
     return SG_OK;
 }
 

@@ -116,6 +116,7 @@ struct sg_grid {
     double *tcol = nullptr, *spec = nullptr, *spec2 = nullptr;  // filter workspaces
     size_t spec_size = 0;
     int* d_flag = nullptr;
+    double* cpart = nullptr;          // constraint-norm partials, 4 per 256 points of the largest shell
     sg::Timing tm;
     hipStream_t cap = nullptr;        // capture stream for the step graph
     hipStream_t side[2] = {nullptr, nullptr};   // forked branches of the captured step
@@ -148,4 +149,7 @@ hipError_t launch_ftheta(const KShell& s, int count, const double* spec, double*
 hipError_t launch_initial(const KShell& s, const double* g10, const double* dg, double* u,
                           double* H, hipStream_t st);
 hipError_t launch_finite_check(const double* u, size_t n, int* flag, hipStream_t st);
+// part: ceil(npts/256) * 4 doubles of workspace; norms: 4 doubles.
+hipError_t launch_constraints(const KShell& s, const double* u, const double* dg, double* part, double* norms,
+                              hipStream_t st);
 }  // namespace sg

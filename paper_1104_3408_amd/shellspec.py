@@ -56,6 +56,7 @@ _SIGS = {
     "spec_derivs": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P]),
     "swsh_filter": (ctypes.c_int, [_P, _P, _P]),
     "ghg_rhs": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "ghg_constraints": (ctypes.c_int, [_P, _P, _P, _P]),
     "rk_step": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P]),
     "sg_kerr_schild_data": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "sg_enable_timing": (ctypes.c_int, [_P, ctypes.c_int]),
@@ -183,6 +184,11 @@ class ShellGrid:
 
     def ghg_rhs(self, u, rhs, du_cart=None, stream=None):
         _check(lib().ghg_rhs(self.h, _ptr(u), _ptr(du_cart), _ptr(rhs), _stream(stream)))
+
+    def ghg_constraints(self, u, norms, stream=None):
+        """norms: device float64 tensor of 4 * n_shells, per shell
+        (max |C_a|, rms C_a, max |C_iab|, rms C_iab)."""
+        _check(lib().ghg_constraints(self.h, _ptr(u), _ptr(norms), _stream(stream)))
 
     def rk_step(self, u, n_steps=1, dt=None, stream=None):
         arr = None

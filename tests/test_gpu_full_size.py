@@ -126,6 +126,16 @@ def test_large8_entry_points_and_step():
     for x in range(3):
         assert rel(got_du[x], du_ref[x]) < TOL, x
 
+    # constraint norms of the sampled shell
+    norms = torch.zeros(4 * len(shells), dtype=torch.float64, device="cuda")
+    g.ghg_constraints(u0, norms)
+    got_c = host(norms).reshape(len(shells), 4)[ks]
+    ref_c = np.array(ghg.constraint_norms(*ghg.constraints(u_ref, du_ref)))
+    print("large8 constraint norms gpu %s oracle %s" % (got_c, ref_c), flush=True)
+    # C_iab is the difference of two spectral derivatives of g here (zero on
+    # the GPU, whose Phi is its own derivative): compare on the state's scale
+    assert np.abs(got_c - ref_c).max() <= TOL * np.abs(u_ref).max()
+
     # right-hand side with the boundary operator at sampled points
     rt = torch.zeros_like(u0)
     g.ghg_rhs(u0, rt)

@@ -319,3 +319,35 @@ def test_mixed_precision_error(n_r, n_th, steps):
                                                                                       bound))
     assert err < bound, (err, bound)
     assert err > 1e-13       # really computed in reduced precision
+
+
+@pytest.mark.parametrize("n_v", [50, 58])
+def test_constraint_norms(n_v):
+    """ghg_constraints against the oracle's C_a, C_iab norms on two shells with
+    planted constraint violations (noise in Pi, Phi and H)."""
+    shells = [(13, 12, 24, 1.8, 11.8), (9, 8, 16, 2.0, 7.0)]
+    g = ss.ShellGrid(shells, n_fields=n_v)
+    rng = np.random.default_rng(21 + n_v)
+    states, Hs = [], []
+    for k, (nr, nt, nph, a, b) in enumerate(shells):
+        sh = Shell(nr, nt, nph, a, b)
+        g10 = inputs.perturbed_kerr_schild(30 + k, sh.r, sh.theta, sh.phi)
+        u = oid.first_order_data(g10, sh)
+        H, _ = oid.static_gauge(u, sh)
+        u[10:50] += 1e-3 * rng.standard_normal(u[10:50].shape)
+        H = H + 1e-3 * rng.standard_normal(H.shape)
+        if n_v == 58:
+            u = np.concatenate([u, H, 1e-3 * rng.standard_normal(H.shape)])
+        states.append((sh, u))
+        Hs.append(H)
+    if n_v == 50:
+        g.set_gauge(dev(np.concatenate([h.ravel() for h in Hs])))
+    ut = dev(np.concatenate([u.ravel() for _, u in states]))
+    norms = torch.zeros(4 * len(shells), dtype=torch.float64, device="cuda")
+    g.ghg_constraints(ut, norms)
+    got = host(norms).reshape(len(shells), 4)
+    for k, (sh, u) in enumerate(states):
+        du = np.array(od.cartesian_derivs(u, sh))
+        ref = np.array(ghg.constraint_norms(*ghg.constraints(u, du, None if n_v == 58 else Hs[k])))
+        assert np.all(ref > 1e-5), ref
+        assert np.abs(got[k] - ref).max() / ref.max() < TOL, (k, got[k], ref)
