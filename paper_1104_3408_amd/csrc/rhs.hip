@@ -65,7 +65,7 @@ __global__ __launch_bounds__(kWaves * 64, 2) void k_rhs(KShell s, const double* 
     __shared__ double sdtg[10][kPts];        // d_t g_ab, eq. gdot
     __shared__ double sC[4][kPts];           // C_a = H_a + Gamma_a
     __shared__ double sHu[4][kPts];          // H^a = g^ab H_b
-    __shared__ double sv[12][kPts];          // n.n.Pi, (n^c Pi_cx gamma^xy)_y, n.n.Phi_x, -
+    __shared__ double sv[7][kPts];           // n.n.Pi, (n^c Pi_cx gamma^xy)_y, n.n.Phi_x
     __shared__ double swu[3][3][kPts];       // n^c Phi_x(y)c gamma^yz
 
     const long long np = s.npts;
@@ -333,48 +333,50 @@ __global__ __launch_bounds__(kWaves * 64, 2) void k_rhs(KShell s, const double* 
         //   = Phi_xac Z_xc - Pi_ac V_c - Gamma_ace Y^ce,
         // with Z_xc = g^cd gamma^xy Phi_ybd, V_c = g^cd Pi_bd and
         // Y = G Gamma_b G (Gamma_b the 4x4 matrix Gamma_bdf), all of row b.
+        // Contractions streamed so that few values are live at a time (the
+        // register budget decides how many workgroups share a CU): Phi part
+        // per spatial x, Pi part per c, Gamma part per column e of G Gamma_b.
         double quad1 = 0.0, quad2 = 0.0, quad3 = 0.0;
-        {
-            double Pb[3][4], pb[4];
 #pragma unroll
-            for (int d = 0; d < 4; ++d) {
-                const double f0 = PH(0, b, d), f1 = PH(1, b, d), f2 = PH(2, b, d);
+        for (int x = 0; x < 3; ++x) {
+            double pbx[4];   // gamma^xy Phi_ybd
 #pragma unroll
-                for (int x = 0; x < 3; ++x) Pb[x][d] = gi[x][0] * f0 + gi[x][1] * f1 + gi[x][2] * f2;
-                pb[d] = PI(b, d);
-            }
+            for (int d = 0; d < 4; ++d) pbx[d] = gi[x][0] * PH(0, b, d) + gi[x][1] * PH(1, b, d) + gi[x][2] * PH(2, b, d);
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                double zc[3];
-#pragma unroll
-                for (int x = 0; x < 3; ++x)
-                    zc[x] = gI[c][0] * Pb[x][0] + gI[c][1] * Pb[x][1] + gI[c][2] * Pb[x][2] + gI[c][3] * Pb[x][3];
-                const double vc = gI[c][0] * pb[0] + gI[c][1] * pb[1] + gI[c][2] * pb[2] + gI[c][3] * pb[3];
-                quad1 += PH(0, a1, c) * zc[0] + PH(1, a1, c) * zc[1] + PH(2, a1, c) * zc[2] - PI(a1, c) * vc;
-                quad2 += PH(0, a2, c) * zc[0] + PH(1, a2, c) * zc[1] + PH(2, a2, c) * zc[2] - PI(a2, c) * vc;
-                if (three) quad3 += PH(0, a3, c) * zc[0] + PH(1, a3, c) * zc[1] + PH(2, a3, c) * zc[2] - PI(a3, c) * vc;
+                const double z = gI[c][0] * pbx[0] + gI[c][1] * pbx[1] + gI[c][2] * pbx[2] + gI[c][3] * pbx[3];
+                quad1 += PH(x, a1, c) * z;
+                quad2 += PH(x, a2, c) * z;
+                if (three) quad3 += PH(x, a3, c) * z;
             }
         }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const double v = gI[c][0] * PI(b, 0) + gI[c][1] * PI(b, 1) + gI[c][2] * PI(b, 2) + gI[c][3] * PI(b, 3);
+            quad1 -= PI(a1, c) * v;
+            quad2 -= PI(a2, c) * v;
+            if (three) quad3 -= PI(a3, c) * v;
+        }
         {
-            double X[4][4];   // X[d][f] = g^de Gamma_bef
-#pragma unroll
-            for (int f = 0; f < 4; ++f) {
-                double gb[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) gb[e] = Gam(b, e, f);
-#pragma unroll
-                for (int d = 0; d < 4; ++d)
-                    X[d][f] = gI[d][0] * gb[0] + gI[d][1] * gb[1] + gI[d][2] * gb[2] + gI[d][3] * gb[3];
-            }
+            double gb[4][4];   // Gamma_bdf (symmetric in d, f)
 #pragma unroll
             for (int d = 0; d < 4; ++d)
 #pragma unroll
-                for (int c = d; c < 4; ++c) {
-                    const double y = (c == d ? 1.0 : 2.0) *
-                                     (X[d][0] * gI[0][c] + X[d][1] * gI[1][c] + X[d][2] * gI[2][c] + X[d][3] * gI[3][c]);
-                    quad1 -= Gam(a1, d, c) * y;
-                    quad2 -= Gam(a2, d, c) * y;
-                    if (three) quad3 -= Gam(a3, d, c) * y;
+                for (int f = d; f < 4; ++f) gb[d][f] = gb[f][d] = Gam(b, d, f);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                double t[4];   // Gamma_bdf g^fe
+#pragma unroll
+                for (int d = 0; d < 4; ++d)
+                    t[d] = gb[d][0] * gI[0][e] + gb[d][1] * gI[1][e] + gb[d][2] * gI[2][e] + gb[d][3] * gI[3][e];
+#pragma unroll
+                for (int c = 0; c <= e; ++c) {   // Y^ce = g^cd t_d, symmetric: off-diagonal twice
+                    const double y = (c == e ? 1.0 : 2.0) *
+                                     (gI[c][0] * t[0] + gI[c][1] * t[1] + gI[c][2] * t[2] + gI[c][3] * t[3]);
+                    quad1 -= Gam(a1, c, e) * y;
+                    quad2 -= Gam(a2, c, e) * y;
+                    if (three) quad3 -= Gam(a3, c, e) * y;
+                }
                 }
         }
         // the barriers keep each pair's derivative loads from being hoisted
