@@ -73,10 +73,13 @@ typedef struct {
                          eq. nfofmu), _NONE */
     int n_f;          /* number of top degrees removed, l <= L - n_f, L = N_theta - 1
                          (Sec. 3.5); the paper's default is 4 */
-    int precision;    /* SG_PREC_FP64, or SG_PREC_FP32: theta and phi derivatives of
-                         rk_step computed and stored in FP32 (state, d_r, rhs, RK
-                         update and filter stay FP64); SG_PREC_BF16X3 returns
-                         SG_EUNSUPPORTED */
+    int precision;    /* SG_PREC_FP64, or SG_PREC_FP32: in rk_step the theta and phi
+                         derivatives are computed and stored in FP32, and the filter
+                         is split as F(u) = F(u_ref) + F(u - u_ref) with F(u_ref)
+                         in FP64 and the difference filtered in FP32 (u_ref: the
+                         state at the first rk_step call on that state array);
+                         d_r, the rhs and the RK state stay FP64.  SG_PREC_BF16X3
+                         returns SG_EUNSUPPORTED */
     double courant;   /* lambda of Delta t = lambda min(Delta x) (Sec. 4.1), e.g. 4 */
     double mass;      /* black-hole mass M used by sg_kerr_schild_data */
     unsigned flags;   /* SG_CHECK_FINITE: rk_step reports NaN/Inf; SG_NO_GRAPH: rk_step

@@ -112,7 +112,7 @@ void free_shell(ShellHost& s) {
     if (!s.owns_ops) return;   // operators shared with an earlier identical shell
     for (double* p : {s.Drb, s.Hsb, s.Hab, s.dph.Wb, s.ana.Wb, s.syn.Wb, s.rk, s.sth, s.cth, s.sph, s.cph, s.Fb})
         if (p) (void)hipFree(p);
-    for (float* p : {s.Hsb_f, s.Hab_f, s.dph.Wb_f, s.ana.Wb_f, s.syn.Wb_f})
+    for (float* p : {s.Hsb_f, s.Hab_f, s.dph.Wb_f, s.ana.Wb_f, s.syn.Wb_f, s.Fb_f})
         if (p) (void)hipFree(p);
 }
 
@@ -235,7 +235,7 @@ hipError_t filter_run(sg_grid* g, const Run& R, double* u, hipStream_t st) {
     }
     {
         TimeScope ts(g, SG_K_FTHETA, st);
-        const FiltPlan fp{S.Fb, g->d_groups, g->d_fsets, (int)g->fsets.size(), g->max_groups, S.F_R};
+        const FiltPlan fp{S.Fb, S.Fb_f, g->d_groups, g->d_fsets, (int)g->fsets.size(), g->max_groups, S.F_R};
         if ((e = launch_ftheta(v, R.count, g->spec, g->spec2, fp, g->n_cols, S.m_keep, st)) != hipSuccess)
             return e;
     }
@@ -248,6 +248,43 @@ hipError_t filter_run(sg_grid* g, const Run& R, double* u, hipStream_t st) {
         return launch_recompose(v, R.count, g->tcol, u, st);
     }
     return hipSuccess;
+}
+
+// Mixed-precision filter of a run by reference splitting: the filter is
+// linear, so F(u) = F(uref) + F(u - uref) with F(uref) formed in FP64 once per
+// rk_step call (furef) and F(u - uref) in FP32 (the difference is small, so
+// its FP32 rounding is small in absolute terms).
+hipError_t filter_run_split(sg_grid* g, const Run& R, double* u, hipStream_t st) {
+    const ShellHost& S = g->sh[R.first];
+    const KShell v = S.view(g->opt.n_fields);
+    const long long ncol = (long long)S.d.n_theta * S.d.n_r;
+    float* tcol = g->tcol32;           // workspaces shared by the runs (they run in order)
+    float* spec = g->spec32;
+    float* spec2 = g->spec2_32;
+    const double* uref = g->uref + S.off;
+    const double* base = g->furef + S.off;
+    hipError_t e;
+    const long long n = (long long)S.count * R.count;
+    {
+        TimeScope ts(g, SG_K_DECOMP, st);
+        e = g->tetrad ? launch_decompose_delta(v, R.count, u, uref, tcol, st) : launch_delta_f32(u, uref, tcol, n, st);
+        if (e != hipSuccess) return e;
+    }
+    {
+        TimeScope ts(g, SG_K_FANA, st);
+        if ((e = launch_axis_ff(S.ana, tcol, spec, ncol, g->n_cols * R.count, st)) != hipSuccess) return e;
+    }
+    {
+        TimeScope ts(g, SG_K_FTHETA, st);
+        const FiltPlan fp{S.Fb, S.Fb_f, g->d_groups, g->d_fsets, (int)g->fsets.size(), g->max_groups, S.F_R};
+        if ((e = launch_ftheta_f32(v, R.count, spec, spec2, fp, g->n_cols, S.m_keep, st)) != hipSuccess) return e;
+    }
+    {
+        TimeScope ts(g, SG_K_FSYN, st);
+        if ((e = launch_axis_ff(S.syn, spec2, tcol, ncol, g->n_cols * R.count, st)) != hipSuccess) return e;
+    }
+    TimeScope ts(g, SG_K_RECOMP, st);
+    return g->tetrad ? launch_recompose_base(v, R.count, tcol, base, u, st) : launch_add_base(tcol, base, u, n, st);
 }
 
 // Runs of consecutive shells with identical grids (and, for a step, equal dt).
@@ -350,7 +387,7 @@ sg_status shell_grid_create(const sg_shell_desc* shells, int n_shells, const sg_
             S.Dr_R = T.Dr_R; S.Hth_R = T.Hth_R;
             S.dph = T.dph; S.ana = T.ana; S.syn = T.syn;
             S.rk = T.rk; S.sth = T.sth; S.cth = T.cth; S.sph = T.sph; S.cph = T.cph;
-            S.Fb = T.Fb; S.F_R = T.F_R;
+            S.Fb = T.Fb; S.Fb_f = T.Fb_f; S.F_R = T.F_R;
             S.owns_ops = false;
             g->sh.push_back(S);
             continue;
@@ -413,7 +450,8 @@ sg_status shell_grid_create(const sg_shell_desc* shells, int n_shells, const sg_
             make_axis(H.ana, ana, H.K, np_) != hipSuccess || make_axis(H.syn, syn, np_, H.K) != hipSuccess ||
             upload(&H.rk, H.r_host) != hipSuccess || upload(&H.sth, sth) != hipSuccess ||
             upload(&H.cth, cth) != hipSuccess || upload(&H.sph, sph) != hipSuccess ||
-            upload(&H.cph, cph) != hipSuccess || upload(&H.Fb, fm) != hipSuccess)
+            upload(&H.cph, cph) != hipSuccess || upload(&H.Fb, fm) != hipSuccess ||
+            upload(&H.Fb_f, to_f(fm)) != hipSuccess)
             return cleanup(SG_ENOMEM, "device allocation/upload of operator matrices failed");
     }
     g->total = off;
@@ -454,6 +492,15 @@ sg_status shell_grid_create(const sg_shell_desc* shells, int n_shells, const sg_
         return cleanup(SG_ENOMEM, "workspace allocation failed");
     if (upload(&g->d_groups, g->groups) != hipSuccess || upload(&g->d_fsets, g->fsets) != hipSuccess)
         return cleanup(SG_ENOMEM, "group upload failed");
+    if (opt->precision == SG_PREC_FP32 && opt->filter_kind != SG_FILTER_NONE) {
+        if (hipMalloc((void**)&g->uref, sizeof(double) * g->total) != hipSuccess ||
+            hipMalloc((void**)&g->furef, sizeof(double) * g->total) != hipSuccess ||
+            hipMalloc((void**)&g->tcol32, sizeof(float) * g->total) != hipSuccess ||
+            hipMalloc((void**)&g->spec32, sizeof(float) * spec) != hipSuccess ||
+            hipMalloc((void**)&g->spec2_32, sizeof(float) * spec) != hipSuccess)
+            return cleanup(SG_ENOMEM, "mixed-precision filter workspace allocation failed");
+        if (hipMemset(g->spec2_32, 0, sizeof(float) * spec) != hipSuccess) return cleanup(SG_EHIP, "memset failed");
+    }
     if (hipMemset(g->spec2, 0, sizeof(double) * spec) != hipSuccess) return cleanup(SG_EHIP, "memset failed");
     if (gauge_H) {
         sg_status s2 = sg_set_gauge(g, gauge_H, nullptr);
@@ -480,7 +527,8 @@ void shell_grid_destroy(sg_grid* g) {
     for (auto& s : g->sh) free_shell(s);
     for (void* p : {(void*)g->us, (void*)g->acc, (void*)g->dbuf, (void*)g->tcol, (void*)g->spec, (void*)g->spec2,
                     (void*)g->d_flag, (void*)g->d_groups, (void*)g->d_fsets, (void*)g->Hall, (void*)g->dHall,
-                    (void*)g->cpart})
+                    (void*)g->cpart, (void*)g->uref, (void*)g->furef, (void*)g->tcol32, (void*)g->spec32,
+                    (void*)g->spec2_32})
         if (p) (void)hipFree(p);
     for (auto e : g->tm.ev) (void)hipEventDestroy(e);
     delete g;
@@ -612,8 +660,10 @@ static hipError_t step_launches(sg_grid* g, double* u, const double* dt, hipStre
                     return e;
             }
         }
-        if (g->opt.filter_kind != SG_FILTER_NONE)
-            if ((e = filter_run(g, R, u0, st)) != hipSuccess) return e;
+        if (g->opt.filter_kind != SG_FILTER_NONE) {
+            e = mixed ? filter_run_split(g, R, u0, st) : filter_run(g, R, u0, st);
+            if (e != hipSuccess) return e;
+        }
     }
     return hipSuccess;
 }
@@ -664,6 +714,14 @@ sg_status rk_step(sg_grid* g, double* u, const double* dt, int n_steps, sg_strea
     }
     std::vector<double> dts(g->sh.size());
     for (size_t s = 0; s < g->sh.size(); ++s) dts[s] = dt ? dt[s] : g->sh[s].dt;
+    if (g->uref && n_steps > 0 && g->ref_of != u) {
+        // mixed precision: the split filter's reference is the state of the
+        // first rk_step call on this state array; F(uref) in FP64
+        HIP_TRY(hipMemcpyAsync(g->uref, u, sizeof(double) * g->total, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(g->furef, u, sizeof(double) * g->total, hipMemcpyDeviceToDevice, st));
+        for (const Run& R : g->runs) HIP_TRY(filter_run(g, R, g->furef + g->sh[R.first].off, st));
+        g->ref_of = u;
+    }
     const bool graph = !g->tm.on && !(g->opt.flags & SG_NO_GRAPH) && n_steps > 0;
     if (graph) {
         if (!g->sgraph.exec || g->sgraph.u != u || g->sgraph.dt != dts) {

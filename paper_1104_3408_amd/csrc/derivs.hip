@@ -202,8 +202,8 @@ __global__ __launch_bounds__(256) void k_dtheta(const double* __restrict__ in, O
 // rounding is relative to the deviation from the mean.
 constexpr int kAxisMaxIn = 128;
 
-template <int R, typename T, typename O>
-__global__ __launch_bounds__(256) void k_axis(const double* __restrict__ in, O* __restrict__ out,
+template <int R, typename I, typename T, typename O>
+__global__ __launch_bounds__(256) void k_axis(const I* __restrict__ in, O* __restrict__ out,
                                               const T* __restrict__ Wb, int n_in, int n_out, int passes,
                                               long long ncol, int center) {
     extern __shared__ double smd[];  // tile [n_in][64] in T, then partial sums [4][64] in FP64
@@ -212,7 +212,7 @@ __global__ __launch_bounds__(256) void k_axis(const double* __restrict__ in, O* 
     const long long c0 = (long long)blockIdx.x * 64;
     const int nc = (int)min((long long)64, ncol - c0);
     const int f = blockIdx.y;
-    const double* src = in + (long long)f * n_in * ncol + c0;
+    const I* src = in + (long long)f * n_in * ncol + c0;
     const int lane = threadIdx.x & 63;
     const int w = wave_id();
     const bool colok = lane < nc;
@@ -220,7 +220,7 @@ __global__ __launch_bounds__(256) void k_axis(const double* __restrict__ in, O* 
     if (sizeof(T) == 8 || !center) {
         double part = 0.0;
         for (int r = w; r < n_in; r += 4) {
-            const double v = colok ? src[(long long)r * ncol + lane] : 0.0;
+            const double v = colok ? (double)src[(long long)r * ncol + lane] : 0.0;
             part += v;
             sm[r * 64 + lane] = (T)v;
         }
@@ -233,7 +233,7 @@ __global__ __launch_bounds__(256) void k_axis(const double* __restrict__ in, O* 
 #pragma unroll
         for (int t = 0; t < kAxisMaxIn / 4; ++t) {
             const int r = w + 4 * t;
-            v[t] = (r < n_in && colok) ? src[(long long)r * ncol + lane] : 0.0;
+            v[t] = (r < n_in && colok) ? (double)src[(long long)r * ncol + lane] : 0.0;
             part += v[t];
         }
         spart[w * 64 + lane] = part;
@@ -353,14 +353,14 @@ hipError_t launch_dtheta_f32(const KShell& s, const double* in, float* out, int 
     return dtheta_t<float, float>(s, in, out, s.Hsb_f, s.Hab_f, n_fields, st);
 }
 
-template <typename T, typename O>
-static hipError_t axis_t(const AxisOp& op, const T* Wb, const double* in, O* out, long long ncol, int n_fields,
+template <typename I, typename T, typename O>
+static hipError_t axis_t(const AxisOp& op, const T* Wb, const I* in, O* out, long long ncol, int n_fields,
                          int center, hipStream_t st) {
     if (op.n_in > kAxisMaxIn) return hipErrorInvalidValue;
     const unsigned bx = (unsigned)((ncol + 63) / 64);
     const size_t shm = sizeof(T) * size_t(op.n_in) * 64 + 4 * 64 * sizeof(double);
     switch (op.R) {
-#define X(R) case R: hipLaunchKernelGGL((k_axis<R, T, O>), dim3(bx, n_fields), dim3(256), shm, st, in, out, Wb, op.n_in, op.n_out, op.passes, ncol, center); break;
+#define X(R) case R: hipLaunchKernelGGL((k_axis<R, I, T, O>), dim3(bx, n_fields), dim3(256), shm, st, in, out, Wb, op.n_in, op.n_out, op.passes, ncol, center); break;
         SG_R_CASES(X)
 #undef X
         default: return hipErrorInvalidValue;
@@ -370,12 +370,17 @@ static hipError_t axis_t(const AxisOp& op, const T* Wb, const double* in, O* out
 
 hipError_t launch_axis(const AxisOp& op, const double* in, double* out, long long ncol, int n_fields, int center,
                        hipStream_t st) {
-    return axis_t<double, double>(op, op.Wb, in, out, ncol, n_fields, center, st);
+    return axis_t<double, double, double>(op, op.Wb, in, out, ncol, n_fields, center, st);
 }
 
 hipError_t launch_axis_f32(const AxisOp& op, const double* in, float* out, long long ncol, int n_fields, int center,
                            hipStream_t st) {
-    return axis_t<float, float>(op, op.Wb_f, in, out, ncol, n_fields, center, st);
+    return axis_t<double, float, float>(op, op.Wb_f, in, out, ncol, n_fields, center, st);
+}
+
+hipError_t launch_axis_ff(const AxisOp& op, const float* in, float* out, long long ncol, int n_fields,
+                          hipStream_t st) {
+    return axis_t<float, float, float>(op, op.Wb_f, in, out, ncol, n_fields, 0, st);
 }
 
 hipError_t launch_chain(const KShell& s, double* du, int n_fields, hipStream_t st) {

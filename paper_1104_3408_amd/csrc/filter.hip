@@ -123,16 +123,26 @@ __device__ __forceinline__ Cx10 sym2_to_cx10(const Sym2& c) {
     return {{c.tt, 0}, {c.tr, 0}, c.tm, conj(c.tm), {c.rr, 0}, c.rm, conj(c.rm), c.mm, conj(c.mm), {c.mmb, 0}};
 }
 
-__global__ __launch_bounds__(256) void k_decompose(KShell s, const double* __restrict__ u, double* __restrict__ t) {
+// With uref the columns of u - uref are formed (in FP64, rounded once to TO).
+template <typename TO>
+__global__ __launch_bounds__(256) void k_decompose(KShell s, const double* __restrict__ u_,
+                                                   const double* __restrict__ uref, TO* __restrict__ t) {
     const long long np = s.npts;
-    u += (long long)blockIdx.y * s.n_v * np;   // shell of a run
-    t += (long long)blockIdx.y * s.n_v * np;
+    const long long so = (long long)blockIdx.y * s.n_v * np;   // shell of a run
+    const double* u0 = u_ + so;
+    const double* ur = uref ? uref + so : nullptr;
+    t += so;
+    struct Src {
+        const double* a;
+        const double* b;
+        __device__ double operator[](long long k) const { return b ? a[k] - b[k] : a[k]; }
+    } u{u0, ur};
     const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np) return;
     const int i = (int)((p / s.n_r) % s.n_th);
     const int j = (int)(p / ((long long)s.n_r * s.n_th));
     const Tetrad e = make_tetrad(s, i, j);
-    auto put = [&](int c, double v) { t[(long long)c * np + p] = v; };
+    auto put = [&](int c, double v) { t[(long long)c * np + p] = (TO)v; };
     auto putc = [&](int c, cx v) { put(c, v.re); put(c + 1, v.im); };
     for (int blk = 0; blk < 2; ++blk) {          // g, Pi
         double T[4][4];
@@ -190,16 +200,30 @@ __global__ __launch_bounds__(256) void k_decompose(KShell s, const double* __res
     }
 }
 
-__global__ __launch_bounds__(256) void k_recompose(KShell s, const double* __restrict__ t, double* __restrict__ u) {
+// With base, u = base + (recomposed columns) (base: the filtered reference).
+template <typename TI>
+__global__ __launch_bounds__(256) void k_recompose(KShell s, const TI* __restrict__ t, const double* __restrict__ base,
+                                                   double* __restrict__ u_) {
     const long long np = s.npts;
-    u += (long long)blockIdx.y * s.n_v * np;   // shell of a run
-    t += (long long)blockIdx.y * s.n_v * np;
+    const long long so = (long long)blockIdx.y * s.n_v * np;   // shell of a run
+    t += so;
+    struct Dst {
+        double* a;
+        const double* b;
+        struct Ref {
+            double* a;
+            const double* b;
+            long long k;
+            __device__ void operator=(double v) const { a[k] = b ? b[k] + v : v; }
+        };
+        __device__ Ref operator[](long long k) const { return Ref{a, b, k}; }
+    } u{u_ + so, base ? base + so : nullptr};
     const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np) return;
     const int i = (int)((p / s.n_r) % s.n_th);
     const int j = (int)(p / ((long long)s.n_r * s.n_th));
     const Tetrad e = make_tetrad(s, i, j);
-    auto get = [&](int c) { return t[(long long)c * np + p]; };
+    auto get = [&](int c) { return (double)t[(long long)c * np + p]; };
     auto getc = [&](int c) { return cx{get(c), get(c + 1)}; };
     for (int blk = 0; blk < 2; ++blk) {
         const int o = 10 * blk;
@@ -250,12 +274,13 @@ __global__ __launch_bounds__(256) void k_recompose(KShell s, const double* __res
 // two passes of two vectors and half the products of S and D.  Real groups
 // filter a and b with F; at m = 0 a complex group filters a^x and a^y with F
 // (F^n_0 = F^{-n}_0).  J F J v is F applied to v reversed, read back reversed.
-template <int R>
+template <int R, typename T>
 __global__ __launch_bounds__(256) void k_ftheta(int n_r, int n_th, int m_keep, int n_cols_state,
-                                                const double* __restrict__ spec, double* __restrict__ spec2,
-                                                const double* __restrict__ Fb, const FiltGroup* __restrict__ groups,
+                                                const T* __restrict__ spec, T* __restrict__ spec2,
+                                                const T* __restrict__ Fb, const FiltGroup* __restrict__ groups,
                                                 const FiltSet* __restrict__ sets, int n_sets) {
-    extern __shared__ double sm[];   // v0, v1: [n_th][64]
+    extern __shared__ double smd[];   // v0, v1: [n_th][64] in T
+    T* sm = reinterpret_cast<T*>(smd);
     const int m = blockIdx.y;
     const FiltSet fs = sets[blockIdx.z % n_sets];
     const int shell = blockIdx.z / n_sets;
@@ -276,14 +301,14 @@ __global__ __launch_bounds__(256) void k_ftheta(int n_r, int n_th, int m_keep, i
     const int k = ok ? (int)(c - (long long)gi * n_r) : 0;
     const FiltGroup G = groups[fs.first + gi];
     const int qa = (m == 0) ? 0 : 2 * m - 1, qb = 2 * m;
-    const double* Fw = Fb + ((long long)(fs.mat * (m_keep + 1) + m) * 4 + w) * n_th * R;
-    double* v0 = sm;
-    double* v1 = sm + n_th * 64;
+    const T* Fw = Fb + ((long long)(fs.mat * (m_keep + 1) + m) * 4 + w) * n_th * R;
+    T* v0 = sm;
+    T* v1 = sm + n_th * 64;
     const bool mix = fs.cplx && m > 0;   // block-uniform
     const bool neg = G.sign < 0;          // F_+ = J F J for a negative spin
     for (int pass = 0; pass < (mix ? 2 : 1); ++pass) {
-        const double* x0;
-        const double* x1 = nullptr;
+        const T* x0;
+        const T* x1 = nullptr;
         bool rev0 = false, rev1 = false;
         if (!fs.cplx) {
             x0 = spec + G.re * col + qa * per_m + k;
@@ -304,10 +329,10 @@ __global__ __launch_bounds__(256) void k_ftheta(int n_r, int n_th, int m_keep, i
         }
         if (pass > 0) __syncthreads();
         for (int ip = w; ip < n_th; ip += 4) {
-            double a = 0.0, b = 0.0;
+            T a = (T)0, b = (T)0;
             if (ok) {
-                const double va = x0[ip * (long long)n_r];
-                const double vb = x1 ? x1[ip * (long long)n_r] : 0.0;
+                const T va = x0[ip * (long long)n_r];
+                const T vb = x1 ? x1[ip * (long long)n_r] : (T)0;
                 a = mix ? va + vb : va;
                 b = mix ? va - vb : vb;
             }
@@ -315,13 +340,13 @@ __global__ __launch_bounds__(256) void k_ftheta(int n_r, int n_th, int m_keep, i
             v1[(rev1 ? n_th - 1 - ip : ip) * 64 + lane] = b;
         }
         __syncthreads();
-        double acc0[R], acc1[R];
+        T acc0[R], acc1[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) acc0[r] = acc1[r] = 0.0;
+        for (int r = 0; r < R; ++r) acc0[r] = acc1[r] = (T)0;
         #pragma unroll 4   // operator loads run ahead of the FMAs (measured against 1, 2, default)
         for (int ip = 0; ip < n_th; ++ip) {
-            const double a = v0[ip * 64 + lane], b = v1[ip * 64 + lane];
-            const double* f = Fw + ip * R;
+            const T a = v0[ip * 64 + lane], b = v1[ip * 64 + lane];
+            const T* f = Fw + ip * R;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 acc0[r] = fma(f[r], a, acc0[r]);
@@ -340,8 +365,8 @@ __global__ __launch_bounds__(256) void k_ftheta(int n_r, int n_th, int m_keep, i
         __syncthreads();
         if (!ok) continue;
         for (int i = w; i < n_th; i += 4) {
-            const double p0 = v0[(rev0 ? n_th - 1 - i : i) * 64 + lane];
-            const double p1 = v1[(rev1 ? n_th - 1 - i : i) * 64 + lane];
+            const T p0 = v0[(rev0 ? n_th - 1 - i : i) * 64 + lane];
+            const T p1 = v1[(rev1 ? n_th - 1 - i : i) * 64 + lane];
             const long long o = (long long)i * n_r + k;
             if (!fs.cplx) {
                 spec2[G.re * col + qa * per_m + o] = p0;
@@ -350,11 +375,11 @@ __global__ __launch_bounds__(256) void k_ftheta(int n_r, int n_th, int m_keep, i
                 spec2[G.re * col + o] = p0;
                 spec2[G.im * col + o] = p1;
             } else if (pass == 0) {
-                spec2[G.re * col + qa * per_m + o] = 0.5 * (p0 + p1);   // a^x'
-                spec2[G.im * col + qb * per_m + o] = 0.5 * (p0 - p1);   // b^y'
+                spec2[G.re * col + qa * per_m + o] = (T)0.5 * (p0 + p1);   // a^x'
+                spec2[G.im * col + qb * per_m + o] = (T)0.5 * (p0 - p1);   // b^y'
             } else {
-                spec2[G.im * col + qa * per_m + o] = 0.5 * (p0 + p1);   // a^y'
-                spec2[G.re * col + qb * per_m + o] = 0.5 * (p0 - p1);   // b^x'
+                spec2[G.im * col + qa * per_m + o] = (T)0.5 * (p0 + p1);   // a^y'
+                spec2[G.re * col + qb * per_m + o] = (T)0.5 * (p0 - p1);   // b^x'
             }
         }
     }
@@ -362,34 +387,82 @@ __global__ __launch_bounds__(256) void k_ftheta(int n_r, int n_th, int m_keep, i
 
 }  // namespace
 
+// Scalar filters (no tetrad): the columns are the Cartesian components.
+__global__ __launch_bounds__(256) void k_delta_f32(const double* __restrict__ u, const double* __restrict__ uref,
+                                                   float* __restrict__ t, long long n) {
+    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (e < n) t[e] = (float)(u[e] - uref[e]);
+}
+
+__global__ __launch_bounds__(256) void k_add_base(const float* __restrict__ t, const double* __restrict__ base,
+                                                  double* __restrict__ u, long long n) {
+    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (e < n) u[e] = base[e] + (double)t[e];
+}
+
+hipError_t launch_delta_f32(const double* u, const double* uref, float* t, long long n, hipStream_t st) {
+    hipLaunchKernelGGL(k_delta_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, u, uref, t, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_base(const float* t, const double* base, double* u, long long n, hipStream_t st) {
+    hipLaunchKernelGGL(k_add_base, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, t, base, u, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_decompose(const KShell& s, int count, const double* u, double* t, hipStream_t st) {
     const dim3 grid((unsigned)((s.npts + 255) / 256), (unsigned)count);
-    hipLaunchKernelGGL(k_decompose, grid, dim3(256), 0, st, s, u, t);
+    hipLaunchKernelGGL(k_decompose<double>, grid, dim3(256), 0, st, s, u, (const double*)nullptr, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_decompose_delta(const KShell& s, int count, const double* u, const double* uref, float* t,
+                                  hipStream_t st) {
+    const dim3 grid((unsigned)((s.npts + 255) / 256), (unsigned)count);
+    hipLaunchKernelGGL(k_decompose<float>, grid, dim3(256), 0, st, s, u, uref, t);
     return hipGetLastError();
 }
 
 hipError_t launch_recompose(const KShell& s, int count, const double* t, double* u, hipStream_t st) {
     const dim3 grid((unsigned)((s.npts + 255) / 256), (unsigned)count);
-    hipLaunchKernelGGL(k_recompose, grid, dim3(256), 0, st, s, t, u);
+    hipLaunchKernelGGL(k_recompose<double>, grid, dim3(256), 0, st, s, t, (const double*)nullptr, u);
     return hipGetLastError();
 }
 
-hipError_t launch_ftheta(const KShell& s, int count, const double* spec, double* spec2, const FiltPlan& fp,
-                         int n_cols, int m_keep, hipStream_t st) {
+hipError_t launch_recompose_base(const KShell& s, int count, const float* t, const double* base, double* u,
+                                 hipStream_t st) {
+    const dim3 grid((unsigned)((s.npts + 255) / 256), (unsigned)count);
+    hipLaunchKernelGGL(k_recompose<float>, grid, dim3(256), 0, st, s, t, base, u);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t ftheta_t(const KShell& s, int count, const T* spec, T* spec2, const T* Fb, const FiltPlan& fp,
+                           int n_cols, int m_keep, hipStream_t st) {
     if (fp.R < 1 || fp.R > 16 || 4 * fp.R < s.n_th) return hipErrorInvalidValue;
     const long long cols = (long long)fp.max_groups * s.n_r;
     const dim3 grid((unsigned)((cols + 63) / 64), (unsigned)(m_keep + 1), (unsigned)(fp.n_sets * count));
-    const size_t shm = sizeof(double) * 2 * size_t(s.n_th) * 64;
+    const size_t shm = sizeof(T) * 2 * size_t(s.n_th) * 64;
     switch (fp.R) {
-#define X(R)                                                                                                         \
-    case R:                                                                                                          \
-        hipLaunchKernelGGL(k_ftheta<R>, grid, dim3(256), shm, st, s.n_r, s.n_th, m_keep, n_cols, spec, spec2, fp.Fb, \
-                           fp.groups, fp.sets, fp.n_sets);                                                           \
+#define X(R)                                                                                                    \
+    case R:                                                                                                     \
+        hipLaunchKernelGGL((k_ftheta<R, T>), grid, dim3(256), shm, st, s.n_r, s.n_th, m_keep, n_cols, spec,    \
+                           spec2, Fb, fp.groups, fp.sets, fp.n_sets);                                           \
         break;
         X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
 #undef X
     }
     return hipGetLastError();
+}
+
+hipError_t launch_ftheta(const KShell& s, int count, const double* spec, double* spec2, const FiltPlan& fp,
+                         int n_cols, int m_keep, hipStream_t st) {
+    return ftheta_t<double>(s, count, spec, spec2, fp.Fb, fp, n_cols, m_keep, st);
+}
+
+hipError_t launch_ftheta_f32(const KShell& s, int count, const float* spec, float* spec2, const FiltPlan& fp,
+                             int n_cols, int m_keep, hipStream_t st) {
+    return ftheta_t<float>(s, count, spec, spec2, fp.Fb_f, fp, n_cols, m_keep, st);
 }
 
 }  // namespace sg

@@ -42,6 +42,7 @@ struct FiltSet {
 // Device view of the theta filter of one shell.
 struct FiltPlan {
     const double* Fb;           // [mat][m][wave][N_theta][R], F^{|n|}_m rows wave-blocked
+    const float* Fb_f;          // FP32 copy (mixed-precision filter)
     const FiltGroup* groups;
     const FiltSet* sets;
     int n_sets, max_groups, R;
@@ -68,6 +69,7 @@ struct ShellHost {
     AxisOp dph, ana, syn;                    // d_phi, Fourier analysis, Fourier synthesis
     double *rk = nullptr, *sth = nullptr, *cth = nullptr, *sph = nullptr, *cph = nullptr;
     double *Fb = nullptr;                    // theta filter matrices, FiltPlan layout
+    float *Fb_f = nullptr;                   // FP32 copy
     int F_R = 0;                             // theta rows per wave of Fb
     double *H = nullptr, *dH = nullptr;      // static gauge
     bool owns_ops = true;                    // false: operators belong to an earlier identical shell
@@ -117,6 +119,11 @@ struct sg_grid {
     size_t spec_size = 0;
     int* d_flag = nullptr;
     double* cpart = nullptr;          // constraint-norm partials, 4 per 256 points of the largest shell
+    // mixed-precision filter (SG_PREC_FP32): reference state, its FP64 filter,
+    // FP32 column and spectral workspaces
+    double *uref = nullptr, *furef = nullptr;
+    float *tcol32 = nullptr, *spec32 = nullptr, *spec2_32 = nullptr;
+    const double* ref_of = nullptr;   // state array the reference was taken from
     sg::Timing tm;
     hipStream_t cap = nullptr;        // capture stream for the step graph
     hipStream_t side[2] = {nullptr, nullptr};   // forked branches of the captured step
@@ -143,6 +150,18 @@ hipError_t launch_rhs(const KShell& s, int count, const double* u, const double*
 hipError_t launch_rhs_mixed(const KShell& s, int count, const double* u, const double* dr, const float* dang,
                             double* out, const double* ubase, double* acc, double dt, int stage, hipStream_t st);
 hipError_t launch_decompose(const KShell& s, int count, const double* u, double* t, hipStream_t st);
+// Mixed-precision filter by reference splitting: columns of u - uref in FP32,
+// and u = base + recomposed FP32 columns (base = the FP64-filtered reference).
+hipError_t launch_decompose_delta(const KShell& s, int count, const double* u, const double* uref, float* t,
+                                  hipStream_t st);
+hipError_t launch_recompose_base(const KShell& s, int count, const float* t, const double* base, double* u,
+                                 hipStream_t st);
+hipError_t launch_delta_f32(const double* u, const double* uref, float* t, long long n, hipStream_t st);
+hipError_t launch_add_base(const float* t, const double* base, double* u, long long n, hipStream_t st);
+hipError_t launch_ftheta_f32(const KShell& s, int count, const float* spec, float* spec2, const FiltPlan& fp,
+                             int n_cols, int m_keep, hipStream_t st);
+hipError_t launch_axis_ff(const AxisOp& op, const float* in, float* out, long long ncol, int n_fields,
+                          hipStream_t st);
 hipError_t launch_recompose(const KShell& s, int count, const double* t, double* u, hipStream_t st);
 hipError_t launch_ftheta(const KShell& s, int count, const double* spec, double* spec2, const FiltPlan& fp,
                          int n_cols, int m_keep, hipStream_t st);

@@ -289,15 +289,17 @@ def test_kernel_timing_classes():
     assert all(m > 0 for m in ms)
 
 
-@pytest.mark.parametrize("n_r,n_th,steps", [(13, 12, 5), (49, 48, 1)])
-def test_mixed_precision_error(n_r, n_th, steps):
-    """SG_PREC_FP32: angular derivatives in FP32 (d_r, rhs, RK state and filter
-    in FP64), against the FP64 oracle.  Stated bound, relative to max|u|: one
-    FP32 rounding unit of the angular operator per step, amplified by the chain
+@pytest.mark.parametrize("n_r,n_th,steps,kind", [(13, 12, 5, "Yn"), (49, 48, 1, "Yn"), (13, 12, 5, "Y")])
+def test_mixed_precision_error(n_r, n_th, steps, kind):
+    """SG_PREC_FP32: angular derivatives in FP32 and the filter split as
+    F(u) = F(u_ref) + F32(u - u_ref) (d_r, rhs and the RK state in FP64),
+    against the FP64 oracle.  Stated bound, relative to max|u|: one FP32
+    rounding unit of the angular operator per step, amplified by the chain
     rule, steps * dt * 2^-24 * ||D||_inf / (r_min sin theta_0); ||D||_inf is the
     row-sum norm of the Fourier derivative on N_phi = 2 N_theta points (the phi
-    matrix and the double-cover theta matrix share it)."""
-    g = ss.ShellGrid([(n_r, n_th, 2 * n_th, 1.8, 11.8)], precision=ss.SG_PREC_FP32)
+    matrix and the double-cover theta matrix share it).  The split filter's
+    rounding is relative to |u - u_ref| and adds nothing visible."""
+    g = ss.ShellGrid([(n_r, n_th, 2 * n_th, 1.8, 11.8)], precision=ss.SG_PREC_FP32, filter=kind)
     sh = Shell(n_r, n_th, 2 * n_th, 1.8, 11.8)
     g10 = inputs.perturbed_kerr_schild(3, sh.r, sh.theta, sh.phi)
     u = oid.first_order_data(g10, sh)
@@ -305,7 +307,7 @@ def test_mixed_precision_error(n_r, n_th, steps):
     g.set_gauge(dev(H))
     ut = dev(u)
     g.rk_step(ut, steps)
-    ev = Evolution(sh, 50, H, dH, 'Yn', 4)
+    ev = Evolution(sh, 50, H, dH, kind, 4)
     ref = u
     dt = g.info(0)[2]
     for _ in range(steps):
