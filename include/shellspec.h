@@ -22,8 +22,10 @@
  * Derivative layout: for each shell, three blocks of that shell's state size
  *   (d_r, d_theta, d_phi, or d_x, d_y, d_z), at offset 3*offset(shell).
  * Ownership: every array argument is caller-owned device memory (for example
- *   a torch tensor); the library never frees or reallocates it.  The grid
- *   object owns its operator matrices and workspaces.
+ *   a torch tensor); the library never frees or reallocates it, and cannot
+ *   check device array sizes: the caller guarantees the sizes stated at each
+ *   entry point (the Python binding checks them).  The grid object owns its
+ *   operator matrices and workspaces.
  * Streams: every compute call is asynchronous and ordered on the given HIP
  *   stream (0 = the null stream); no hidden host synchronisation happens on
  *   the hot calls.  Calls on one grid object must not overlap in time: they
@@ -157,7 +159,8 @@ sg_status ghg_rhs(sg_grid* g, const double* u, const double* du_cart, double* rh
 /* n_steps classical RK4 steps of the method of lines (Sec. 2.5), u in place:
  * four right-hand-side evaluations (derivatives, rhs, boundary operator),
  * then the filter after each full step.  dt: host array with one time step
- * per shell, or NULL for each shell's Courant step.  One step is captured
+ * per shell (finite and > 0, else SG_EINVAL), or NULL for each shell's Courant
+ * step.  One step is captured
  * into a HIP graph (on a private stream, re-captured when u or dt change)
  * and replayed n_steps times on the given stream, unless SG_NO_GRAPH is set
  * or kernel timing is enabled.  With SG_CHECK_FINITE the

@@ -713,7 +713,10 @@ sg_status rk_step(sg_grid* g, double* u, const double* dt, int n_steps, sg_strea
         g->tm.cls.clear();
     }
     std::vector<double> dts(g->sh.size());
-    for (size_t s = 0; s < g->sh.size(); ++s) dts[s] = dt ? dt[s] : g->sh[s].dt;
+    for (size_t s = 0; s < g->sh.size(); ++s) {
+        dts[s] = dt ? dt[s] : g->sh[s].dt;
+        if (!(dts[s] > 0.0) || !std::isfinite(dts[s])) return fail(SG_EINVAL, "dt must be finite and positive");
+    }
     if (g->uref && n_steps > 0 && g->ref_of != u) {
         // mixed precision: the split filter's reference is the state of the
         // first rk_step call on this state array; F(uref) in FP64

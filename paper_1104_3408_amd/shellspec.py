@@ -90,7 +90,9 @@ def _check(status):
         raise ShellSpecError(status, lib().sg_last_error().decode())
 
 
-def _ptr(x):
+def _ptr(x, n=None):
+    """Device pointer of a contiguous float64 CUDA tensor holding at least n
+    values (raw integer addresses pass through unchecked)."""
     if x is None:
         return None
     if isinstance(x, int):
@@ -98,6 +100,8 @@ def _ptr(x):
     import torch
     if not (x.is_cuda and x.dtype == torch.float64 and x.is_contiguous()):
         raise TypeError("expected a contiguous float64 CUDA tensor")
+    if n is not None and x.numel() < n:
+        raise ValueError("tensor holds %d values, the call needs %d" % (x.numel(), n))
     return x.data_ptr()
 
 
@@ -145,6 +149,7 @@ class ShellGrid:
         self.h = h
         self.shells = [tuple(s) for s in shells]
         self.n_fields = n_fields
+        self.n_points = sum(int(a) * int(b) * int(c) for (a, b, c, _, _) in self.shells)
 
     def close(self):
         if getattr(self, "h", None):
@@ -174,30 +179,37 @@ class ShellGrid:
         return self.info(-1)[1]
 
     def set_gauge(self, H, stream=None):
-        _check(lib().sg_set_gauge(self.h, _ptr(H), _stream(stream)))
+        _check(lib().sg_set_gauge(self.h, _ptr(H, 4 * self.n_points), _stream(stream)))
 
     def spec_derivs(self, u, du, mode=SG_COORD, stream=None):
-        _check(lib().spec_derivs(self.h, _ptr(u), _ptr(du), mode, _stream(stream)))
+        n = self.state_size
+        _check(lib().spec_derivs(self.h, _ptr(u, n), _ptr(du, 3 * n), mode, _stream(stream)))
 
     def swsh_filter(self, u, stream=None):
-        _check(lib().swsh_filter(self.h, _ptr(u), _stream(stream)))
+        _check(lib().swsh_filter(self.h, _ptr(u, self.state_size), _stream(stream)))
 
     def ghg_rhs(self, u, rhs, du_cart=None, stream=None):
-        _check(lib().ghg_rhs(self.h, _ptr(u), _ptr(du_cart), _ptr(rhs), _stream(stream)))
+        n = self.state_size
+        _check(lib().ghg_rhs(self.h, _ptr(u, n), _ptr(du_cart, 3 * n), _ptr(rhs, n), _stream(stream)))
 
     def ghg_constraints(self, u, norms, stream=None):
         """norms: device float64 tensor of 4 * n_shells, per shell
         (max |C_a|, rms C_a, max |C_iab|, rms C_iab)."""
-        _check(lib().ghg_constraints(self.h, _ptr(u), _ptr(norms), _stream(stream)))
+        _check(lib().ghg_constraints(self.h, _ptr(u, self.state_size), _ptr(norms, 4 * len(self.shells)),
+                                     _stream(stream)))
 
     def rk_step(self, u, n_steps=1, dt=None, stream=None):
         arr = None
         if dt is not None:
+            if len(dt) != len(self.shells):
+                raise ValueError("dt needs one time step per shell")
             arr = (ctypes.c_double * len(dt))(*[float(x) for x in dt])
-        _check(lib().rk_step(self.h, _ptr(u), arr, int(n_steps), _stream(stream)))
+        _check(lib().rk_step(self.h, _ptr(u, self.state_size), arr, int(n_steps), _stream(stream)))
 
     def kerr_schild_data(self, g10, u, extra8=None, H_out=None, stream=None):
-        _check(lib().sg_kerr_schild_data(self.h, _ptr(g10), _ptr(extra8), _ptr(u), _ptr(H_out), _stream(stream)))
+        n = self.n_points
+        _check(lib().sg_kerr_schild_data(self.h, _ptr(g10, 10 * n), _ptr(extra8, 8 * n), _ptr(u, self.state_size),
+                                         _ptr(H_out, 4 * n), _stream(stream)))
 
     def enable_timing(self, on=True):
         _check(lib().sg_enable_timing(self.h, 1 if on else 0))

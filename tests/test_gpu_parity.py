@@ -353,3 +353,24 @@ def test_constraint_norms(n_v):
         ref = np.array(ghg.constraint_norms(*ghg.constraints(u, du, None if n_v == 58 else Hs[k])))
         assert np.all(ref > 1e-5), ref
         assert np.abs(got[k] - ref).max() / ref.max() < TOL, (k, got[k], ref)
+
+
+def test_argument_checks():
+    """Wrong sizes are refused by the binding, bad time steps by the library;
+    the state is untouched."""
+    g, sh, g10 = _ks_case(9, 8)
+    ut = torch.zeros(50 * sh.npts, dtype=torch.float64, device="cuda")
+    g.kerr_schild_data(dev(g10), ut)
+    before = ut.clone()
+    with pytest.raises(ValueError):
+        g.rk_step(ut[:-1].contiguous(), 1)
+    with pytest.raises(ValueError):
+        g.rk_step(ut, 1, dt=[0.1, 0.1])
+    with pytest.raises(ss.ShellSpecError) as e:
+        g.rk_step(ut, 1, dt=[-0.1])
+    assert e.value.status == ss.SG_EINVAL
+    with pytest.raises(ss.ShellSpecError):
+        g.rk_step(ut, 1, dt=[float("nan")])
+    with pytest.raises(ValueError):
+        g.spec_derivs(ut, torch.zeros(ut.numel(), dtype=torch.float64, device="cuda"))
+    assert torch.equal(ut, before)

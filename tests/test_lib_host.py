@@ -86,3 +86,14 @@ def test_host_theta_matrix_is_double_cover(n):
     FD = fourier_diff_matrix(2 * n)
     expect = np.concatenate([FD[:n, :n], FD[:n, n:][:, ::-1]], axis=1)
     assert np.abs(H - expect).max() < 1e-13 * np.abs(FD).max()
+
+
+def test_binding_rejects_wrong_sizes_before_any_call():
+    """The binding checks tensor kinds and sizes on the host (CPU tensors are
+    refused before the library is reached; no GPU is needed)."""
+    torch = pytest.importorskip("torch")
+    with pytest.raises(TypeError):
+        ss._ptr(torch.zeros(4, dtype=torch.float64))          # not a CUDA tensor
+    with pytest.raises(TypeError):
+        ss._ptr(torch.zeros(4, dtype=torch.float32))
+    assert ss._ptr(None) is None and ss._ptr(1234) == 1234
