@@ -397,9 +397,7 @@ sg_status shell_grid_create(const sg_shell_desc* shells, int n_shells, const sg_
         std::vector<double> sth(nt), cth(nt), sph(np_), cph(np_);
         for (int i = 0; i < nt; ++i) { sth[i] = std::sin(H.th_host[i]); cth[i] = std::cos(H.th_host[i]); }
         for (int j = 0; j < np_; ++j) { sph[j] = std::sin(H.ph_host[j]); cph[j] = std::cos(H.ph_host[j]); }
-        std::vector<double> fd = fourier_column(np_), Dph(size_t(np_) * np_);
-        for (int a = 0; a < np_; ++a)
-            for (int b = 0; b < np_; ++b) Dph[size_t(a) * np_ + b] = fd[((a - b) % np_ + np_) % np_];
+        const std::vector<double> fd = fourier_column(np_);
         std::vector<double> ana, syn;
         fourier_real_matrices(np_, H.m_keep, ana, syn);
         // theta filters F^{|n|}_m, rows blocked over the 4 waves of k_ftheta
@@ -435,6 +433,19 @@ sg_status shell_grid_create(const sg_shell_desc* shells, int n_shells, const sg_
         blocked_shape(nt, H.Hth_R, passes);
         std::vector<double> Hsb = block_operator(Hs, nt, nt, H.Hth_R, 1), Hab = block_operator(Ha, nt, nt, H.Hth_R, 1);
         auto to_f = [](const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); };
+        // the Fourier derivative along phi is circulant: upload the doubled
+        // column vector, padded for the rows past n of the last wave
+        auto make_circ = [&](AxisOp& op, const std::vector<double>& col, int n) {
+            op.n_in = n;
+            op.n_out = n;
+            op.circ = 1;
+            blocked_shape(n, op.R, op.passes);
+            std::vector<double> dv(size_t(2 * n + 4 * op.R * op.passes), 0.0);
+            for (int t = 0; t < 2 * n; ++t) dv[t] = col[((t - n) % n + n) % n];
+            hipError_t e = upload(&op.Wb, dv);
+            if (e != hipSuccess) return e;
+            return upload(&op.Wb_f, to_f(dv));
+        };
         auto make_axis = [&](AxisOp& op, const std::vector<double>& W, int n_out, int n_in) {
             op.n_in = n_in;
             op.n_out = n_out;
@@ -446,7 +457,7 @@ sg_status shell_grid_create(const sg_shell_desc* shells, int n_shells, const sg_
         };
         if (upload(&H.Drb, Drb) != hipSuccess || upload(&H.Hsb, Hsb) != hipSuccess ||
             upload(&H.Hab, Hab) != hipSuccess || upload(&H.Hsb_f, to_f(Hsb)) != hipSuccess ||
-            upload(&H.Hab_f, to_f(Hab)) != hipSuccess || make_axis(H.dph, Dph, np_, np_) != hipSuccess ||
+            upload(&H.Hab_f, to_f(Hab)) != hipSuccess || make_circ(H.dph, fd, np_) != hipSuccess ||
             make_axis(H.ana, ana, H.K, np_) != hipSuccess || make_axis(H.syn, syn, np_, H.K) != hipSuccess ||
             upload(&H.rk, H.r_host) != hipSuccess || upload(&H.sth, sth) != hipSuccess ||
             upload(&H.cth, cth) != hipSuccess || upload(&H.sph, sph) != hipSuccess ||

@@ -202,7 +202,7 @@ __global__ __launch_bounds__(256) void k_dtheta(const double* __restrict__ in, O
 // rounding is relative to the deviation from the mean.
 constexpr int kAxisMaxIn = 128;
 
-template <int R, typename I, typename T, typename O>
+template <int R, typename I, typename T, typename O, bool CIRC>
 __global__ __launch_bounds__(256) void k_axis(const I* __restrict__ in, O* __restrict__ out,
                                               const T* __restrict__ Wb, int n_in, int n_out, int passes,
                                               long long ncol, int center) {
@@ -251,14 +251,17 @@ __global__ __launch_bounds__(256) void k_axis(const I* __restrict__ in, O* __res
     // operator rows are wave-uniform: scalar loads (an LDS copy with
     // broadcast reads measured 1.9x slower at N_phi = 64)
     for (int p = 0; p < passes; ++p) {
-        const T* Ww = Wb + (long long)(p * 4 + w) * n_in * R;
+        // blocked copy: rows of this wave for input ri at Ww + ri R; circulant:
+        // the sliding window dv[n_in + q0 - ri ...] of a vector that stays in
+        // the scalar cache
+        const T* Ww = CIRC ? Wb + n_in + (p * 4 + w) * R : Wb + (long long)(p * 4 + w) * n_in * R;
         T acc[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) acc[r] = (T)0;
         #pragma unroll 4   // operator loads run ahead of the FMAs (measured against 1, 2, default)
         for (int ri = 0; ri < n_in; ++ri) {
             const T v = sm[ri * 64 + lane] - mt;   // mt = 0 for FP32 tiles
-            const T* wr = Ww + ri * R;
+            const T* wr = CIRC ? Ww - ri : Ww + ri * R;
 #pragma unroll
             for (int r = 0; r < R; ++r) acc[r] = fma(wr[r], v, acc[r]);
         }
@@ -360,7 +363,15 @@ static hipError_t axis_t(const AxisOp& op, const T* Wb, const I* in, O* out, lon
     const unsigned bx = (unsigned)((ncol + 63) / 64);
     const size_t shm = sizeof(T) * size_t(op.n_in) * 64 + 4 * 64 * sizeof(double);
     switch (op.R) {
-#define X(R) case R: hipLaunchKernelGGL((k_axis<R, I, T, O>), dim3(bx, n_fields), dim3(256), shm, st, in, out, Wb, op.n_in, op.n_out, op.passes, ncol, center); break;
+#define X(R)                                                                                                    \
+    case R:                                                                                                     \
+        if (op.circ)                                                                                            \
+            hipLaunchKernelGGL((k_axis<R, I, T, O, true>), dim3(bx, n_fields), dim3(256), shm, st, in, out, Wb, \
+                               op.n_in, op.n_out, op.passes, ncol, center);                                     \
+        else                                                                                                    \
+            hipLaunchKernelGGL((k_axis<R, I, T, O, false>), dim3(bx, n_fields), dim3(256), shm, st, in, out,    \
+                               Wb, op.n_in, op.n_out, op.passes, ncol, center);                                 \
+        break;
         SG_R_CASES(X)
 #undef X
         default: return hipErrorInvalidValue;

@@ -53,6 +53,10 @@ struct AxisOp {
     double* Wb = nullptr;
     float* Wb_f = nullptr;          // FP32 copy for the mixed-precision path
     int n_in = 0, n_out = 0, R = 0, passes = 0;
+    // circ: W is circulant, W[q][c] = v[(q - c) mod n], and Wb holds the
+    // doubled vector dv[t] = v[(t - n) mod n] (zero-padded for padding rows),
+    // so the R weights of a wave for input c are dv[n + q0 - c .. + R - 1]
+    int circ = 0;
 };
 
 // Largest number of output rows one wave accumulates per pass.
