@@ -321,6 +321,8 @@ KShell ShellHost::view(int n_v) const {
     k.Hab = Hab;
     k.Dr_R = Dr_R;
     k.Hth_R = Hth_R;
+    k.Dr_nw = Dr_nw;
+    k.Hth_nw = Hth_nw;
     k.Hsb_f = Hsb_f;
     k.Hab_f = Hab_f;
     k.rk = rk;
@@ -384,7 +386,7 @@ sg_status shell_grid_create(const sg_shell_desc* shells, int n_shells, const sg_
         if (twin >= 0) {
             const ShellHost& T = g->sh[twin];
             S.Drb = T.Drb; S.Hsb = T.Hsb; S.Hab = T.Hab; S.Hsb_f = T.Hsb_f; S.Hab_f = T.Hab_f;
-            S.Dr_R = T.Dr_R; S.Hth_R = T.Hth_R;
+            S.Dr_R = T.Dr_R; S.Hth_R = T.Hth_R; S.Dr_nw = T.Dr_nw; S.Hth_nw = T.Hth_nw;
             S.dph = T.dph; S.ana = T.ana; S.syn = T.syn;
             S.rk = T.rk; S.sth = T.sth; S.cth = T.cth; S.sph = T.sph; S.cph = T.cph;
             S.Fb = T.Fb; S.Fb_f = T.Fb_f; S.F_R = T.F_R;
@@ -401,15 +403,15 @@ sg_status shell_grid_create(const sg_shell_desc* shells, int n_shells, const sg_
         std::vector<double> ana, syn;
         fourier_real_matrices(np_, H.m_keep, ana, syn);
         // theta filters F^{|n|}_m, rows blocked over the 4 waves of k_ftheta
-        H.F_R = (nt + 3) / 4;
-        const size_t per_mat = size_t(4) * nt * H.F_R;
+        H.F_R = (nt + kFiltWaves - 1) / kFiltWaves;
+        const size_t per_mat = size_t(kFiltWaves) * nt * H.F_R;
         std::vector<double> fm(size_t(g->n_sets) * (H.m_keep + 1) * per_mat, 0.0);
         for (int k = 0; k < g->n_sets; ++k) {
             const int n = set_spin(g, k), nf = set_nf(g, k);
             for (int m = 0; m <= H.m_keep; ++m) {
                 const std::vector<double> F = filter_matrix(n, m, nt, nf);
                 double* Fb = fm.data() + (size_t(k) * (H.m_keep + 1) + m) * per_mat;
-                for (int w = 0; w < 4; ++w)
+                for (int w = 0; w < kFiltWaves; ++w)
                     for (int ip = 0; ip < nt; ++ip)
                         for (int r = 0; r < H.F_R; ++r) {
                             const int i = w * H.F_R + r;
@@ -424,14 +426,14 @@ sg_status shell_grid_create(const sg_shell_desc* shells, int n_shells, const sg_
                 Hs[size_t(a) * nt + b] = hl + hr;
                 Ha[size_t(a) * nt + b] = hl - hr;
             }
-        int passes = 0;
-        blocked_shape(nr, H.Dr_R, passes);
-        int passes_th = 0;
-        blocked_shape(nt, H.Hth_R, passes_th);
-        if (passes != 1 || passes_th != 1) return cleanup(SG_ESHAPE, "radial or theta operator needs more than one pass");
-        std::vector<double> Drb = block_operator(cheb_matrix(nr, H.d.r_min, H.d.r_max), nr, nr, H.Dr_R, 1);
-        blocked_shape(nt, H.Hth_R, passes);
-        std::vector<double> Hsb = block_operator(Hs, nt, nt, H.Hth_R, 1), Hab = block_operator(Ha, nt, nt, H.Hth_R, 1);
+        int passes = 0, passes_th = 0;
+        if (blocked_shape(nr, kDrRows, H.Dr_R, passes) != 0 || blocked_shape(nt, kThRows, H.Hth_R, passes_th) != 0)
+            return cleanup(SG_ESHAPE, "radial or theta operator too large for one workgroup");
+        H.Dr_nw = 4 * passes;
+        H.Hth_nw = 4 * passes_th;
+        std::vector<double> Drb = block_operator(cheb_matrix(nr, H.d.r_min, H.d.r_max), nr, nr, H.Dr_R, passes);
+        std::vector<double> Hsb = block_operator(Hs, nt, nt, H.Hth_R, passes_th),
+                            Hab = block_operator(Ha, nt, nt, H.Hth_R, passes_th);
         auto to_f = [](const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); };
         // the Fourier derivative along phi is circulant: upload the doubled
         // column vector, padded for the rows past n of the last wave
@@ -439,7 +441,7 @@ sg_status shell_grid_create(const sg_shell_desc* shells, int n_shells, const sg_
             op.n_in = n;
             op.n_out = n;
             op.circ = 1;
-            blocked_shape(n, op.R, op.passes);
+            if (blocked_shape(n, kAxisRows, op.R, op.passes) != 0) return hipErrorInvalidValue;
             std::vector<double> dv(size_t(2 * n + 4 * op.R * op.passes), 0.0);
             for (int t = 0; t < 2 * n; ++t) dv[t] = col[((t - n) % n + n) % n];
             hipError_t e = upload(&op.Wb, dv);
@@ -449,7 +451,7 @@ sg_status shell_grid_create(const sg_shell_desc* shells, int n_shells, const sg_
         auto make_axis = [&](AxisOp& op, const std::vector<double>& W, int n_out, int n_in) {
             op.n_in = n_in;
             op.n_out = n_out;
-            blocked_shape(n_out, op.R, op.passes);
+            if (blocked_shape(n_out, kAxisRows, op.R, op.passes) != 0) return hipErrorInvalidValue;
             std::vector<double> Wb = block_operator(W, n_out, n_in, op.R, op.passes);
             hipError_t e = upload(&op.Wb, Wb);
             if (e != hipSuccess) return e;

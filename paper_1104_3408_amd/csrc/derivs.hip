@@ -13,9 +13,13 @@
 // padding the data.)
 //
 // Operators are stored wave-blocked and zero-padded by the host:
-// Wb[p][w][c][r] = W[(p * 4 + w) * R + r][c] (0 past the last row), so the R
-// weights one wave needs for input c are contiguous and the inner loops carry
-// no bounds checks.
+// Wb[w][c][r] = W[w * R + r][c] (0 past the last row), so the R weights one
+// wave needs for input c are contiguous and the inner loops carry no bounds
+// checks.  A workgroup has nw = 8, 12 or 16 waves (blocked_shape picks nw and
+// R from a target number of rows per wave): more waves per staged tile
+// shorten each wave's load and FMA chains, which bound these kernels when a
+// shell gives only a few workgroups per CU (measured against 4 waves with up
+// to 20 rows each: d_phi 2.02 -> 1.44 ms on 8 shells of 65x64x128).
 //
 //   d_r      columns = radial lines (contiguous), tile transposed in LDS;
 //   d_theta  columns = (variable, phi_j with j < N_phi/2, r_k); the two
@@ -45,7 +49,7 @@ __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane
 constexpr int kDrStride = 65;
 
 template <int R>
-__global__ __launch_bounds__(256) void k_dr(const double* __restrict__ in, double* __restrict__ out,
+__global__ __launch_bounds__(1024) void k_dr(const double* __restrict__ in, double* __restrict__ out,
                                             const double* __restrict__ Db, int n_r, long long n_lines) {
     extern __shared__ double sm[];   // [n_r][kDrStride]
     const long long line0 = (long long)blockIdx.x * 64;
@@ -56,7 +60,7 @@ __global__ __launch_bounds__(256) void k_dr(const double* __restrict__ in, doubl
     // (e + 1/2)/n_r in FP32 is at least 1/(2 n_r) from an integer and its
     // rounding error (< 1e-5) cannot move the floor
     const float inv_nr = 1.0f / (float)n_r;
-    for (int e = threadIdx.x; e < 64 * n_r; e += 256) {
+    for (int e = threadIdx.x; e < 64 * n_r; e += blockDim.x) {
         const int l = (int)(((float)e + 0.5f) * inv_nr), k = e - l * n_r;
         sm[k * kDrStride + l] = (e < ne) ? src[e] : 0.0;
     }
@@ -82,7 +86,7 @@ __global__ __launch_bounds__(256) void k_dr(const double* __restrict__ in, doubl
     }
     __syncthreads();
     double* dst = out + line0 * n_r;
-    for (int e = threadIdx.x; e < ne; e += 256) {
+    for (int e = threadIdx.x; e < ne; e += blockDim.x) {
         const int l = (int)(((float)e + 0.5f) * inv_nr), k = e - l * n_r;
         dst[e] = sm[k * kDrStride + l];
     }
@@ -92,13 +96,13 @@ __global__ __launch_bounds__(256) void k_dr(const double* __restrict__ in, doubl
 // columns per workgroup, wave w computes theta rows i = w R + r.  The mean
 // of each meridian circle is removed first (the rows of the Fourier matrix
 // sum to zero), in FP64 before any rounding to T: S_i - (sum_i S_i)/N_theta.
-constexpr int kThMaxPerThread = 16;   // N_theta <= 64 rows over 4 waves
+constexpr int kThMaxPerThread = 64 / kMinWaves;   // N_theta <= 64 rows over at least kMinWaves waves
 
 template <int R, typename T, typename O>
-__global__ __launch_bounds__(256) void k_dtheta(const double* __restrict__ in, O* __restrict__ out,
+__global__ __launch_bounds__(1024) void k_dtheta(const double* __restrict__ in, O* __restrict__ out,
                                                 const T* __restrict__ Hsb, const T* __restrict__ Hab,
                                                 int n_r, int n_th, int n_ph, long long n_cols) {
-    extern __shared__ double smd[];  // S [n_th][64], A [n_th][64] in T, then partial sums [4][64] in FP64
+    extern __shared__ double smd[];  // S [n_th][64], A [n_th][64] in T, then partial sums [nw][64] in FP64
     T* sm = reinterpret_cast<T*>(smd);
     T* sS = sm;
     T* sA = sm + n_th * 64;
@@ -106,9 +110,10 @@ __global__ __launch_bounds__(256) void k_dtheta(const double* __restrict__ in, O
     const int half = n_ph / 2;
     const long long plane = (long long)n_th * n_r;
     const long long c0 = (long long)blockIdx.x * 64;
-    // this thread's column; it loads rows ip = w, w + 4, ...
+    // this thread's column; it loads rows ip = w, w + nw, ...
     const int lane = threadIdx.x & 63;
     const int w = wave_id();
+    const int nw = blockDim.x >> 6;
     const long long c = c0 + lane;
     const bool cok = c < n_cols;
     long long f = 0;
@@ -123,7 +128,7 @@ __global__ __launch_bounds__(256) void k_dtheta(const double* __restrict__ in, O
     double ms = 0.0;   // circle mean of S (subtracted per lane for FP64 tiles)
     if (sizeof(T) == 8) {
         double part = 0.0;
-        for (int ip = w; ip < n_th; ip += 4) {
+        for (int ip = w; ip < n_th; ip += nw) {
             double a = 0.0, b = 0.0;
             if (cok) {
                 a = base[(long long)ip * n_r];
@@ -135,13 +140,14 @@ __global__ __launch_bounds__(256) void k_dtheta(const double* __restrict__ in, O
         }
         spart[w * 64 + lane] = part;
         __syncthreads();
-        ms = (spart[lane] + spart[64 + lane] + spart[128 + lane] + spart[192 + lane]) / n_th;
+        for (int v = 0; v < nw; ++v) ms += spart[v * 64 + lane];
+        ms /= n_th;
     } else {
         double sv[kThMaxPerThread], av[kThMaxPerThread];
         double part = 0.0;
 #pragma unroll
         for (int t = 0; t < kThMaxPerThread; ++t) {
-            const int ip = w + 4 * t;
+            const int ip = w + nw * t;
             double a = 0.0, b = 0.0;
             if (cok && ip < n_th) {
                 a = base[(long long)ip * n_r];
@@ -153,10 +159,12 @@ __global__ __launch_bounds__(256) void k_dtheta(const double* __restrict__ in, O
         }
         spart[w * 64 + lane] = part;
         __syncthreads();
-        const double mc = (spart[lane] + spart[64 + lane] + spart[128 + lane] + spart[192 + lane]) / n_th;
+        double mc = 0.0;
+        for (int v = 0; v < nw; ++v) mc += spart[v * 64 + lane];
+        mc /= n_th;
 #pragma unroll
         for (int t = 0; t < kThMaxPerThread; ++t) {
-            const int ip = w + 4 * t;
+            const int ip = w + nw * t;
             if (ip < n_th) {
                 sS[ip * 64 + lane] = (T)(sv[t] - mc);
                 sA[ip * 64 + lane] = (T)av[t];
@@ -194,19 +202,19 @@ __global__ __launch_bounds__(256) void k_dtheta(const double* __restrict__ in, O
 }
 
 // out[f][q][c] = sum_r W[q][r] (in[f][r][c] - m_c),  m_c = mean of column c
-// over r if center, else 0.  grid: (ceil(ncol/64), n_fields); in pass p wave
-// w computes rows q = (p * 4 + w) * R + r.  Thread (w, c) loads rows
-// r = w, w + 4, ... of column c once; the column mean is formed in FP64 from
-// the four waves' partial sums.  FP64 tiles keep the raw values and subtract
+// over r if center, else 0.  grid: (ceil(ncol/64), n_fields); wave w of nw
+// computes rows q = w R + r.  Thread (w, c) loads rows r = w, w + nw, ... of
+// column c once; the column mean is formed in FP64 from the waves' partial
+// sums.  FP64 tiles keep the raw values and subtract
 // the mean per lane; FP32 tiles store (value - mean) rounded once, so the
 // rounding is relative to the deviation from the mean.
 constexpr int kAxisMaxIn = 128;
 
 template <int R, typename I, typename T, typename O, bool CIRC>
-__global__ __launch_bounds__(256) void k_axis(const I* __restrict__ in, O* __restrict__ out,
-                                              const T* __restrict__ Wb, int n_in, int n_out, int passes,
-                                              long long ncol, int center) {
-    extern __shared__ double smd[];  // tile [n_in][64] in T, then partial sums [4][64] in FP64
+__global__ __launch_bounds__(1024) void k_axis(const I* __restrict__ in, O* __restrict__ out,
+                                               const T* __restrict__ Wb, int n_in, int n_out, long long ncol,
+                                               int center) {
+    extern __shared__ double smd[];  // tile [n_in][64] in T, then partial sums [nw][64] in FP64
     T* sm = reinterpret_cast<T*>(smd);
     double* spart = reinterpret_cast<double*>(sm + n_in * 64);
     const long long c0 = (long long)blockIdx.x * 64;
@@ -215,33 +223,39 @@ __global__ __launch_bounds__(256) void k_axis(const I* __restrict__ in, O* __res
     const I* src = in + (long long)f * n_in * ncol + c0;
     const int lane = threadIdx.x & 63;
     const int w = wave_id();
+    const int nw = blockDim.x >> 6;
     const bool colok = lane < nc;
     double m = 0.0;
     if (sizeof(T) == 8 || !center) {
         double part = 0.0;
-        for (int r = w; r < n_in; r += 4) {
+        for (int r = w; r < n_in; r += nw) {
             const double v = colok ? (double)src[(long long)r * ncol + lane] : 0.0;
             part += v;
             sm[r * 64 + lane] = (T)v;
         }
         if (center) spart[w * 64 + lane] = part;
         __syncthreads();
-        if (center) m = (spart[lane] + spart[64 + lane] + spart[128 + lane] + spart[192 + lane]) / n_in;
+        if (center) {
+            for (int v = 0; v < nw; ++v) m += spart[v * 64 + lane];
+            m /= n_in;
+        }
     } else {
-        double v[kAxisMaxIn / 4];
+        double v[kAxisMaxIn / kMinWaves];
         double part = 0.0;
 #pragma unroll
-        for (int t = 0; t < kAxisMaxIn / 4; ++t) {
-            const int r = w + 4 * t;
+        for (int t = 0; t < kAxisMaxIn / kMinWaves; ++t) {
+            const int r = w + nw * t;
             v[t] = (r < n_in && colok) ? (double)src[(long long)r * ncol + lane] : 0.0;
             part += v[t];
         }
         spart[w * 64 + lane] = part;
         __syncthreads();
-        const double mc = (spart[lane] + spart[64 + lane] + spart[128 + lane] + spart[192 + lane]) / n_in;
+        double mc = 0.0;
+        for (int q = 0; q < nw; ++q) mc += spart[q * 64 + lane];
+        mc /= n_in;
 #pragma unroll
-        for (int t = 0; t < kAxisMaxIn / 4; ++t) {
-            const int r = w + 4 * t;
+        for (int t = 0; t < kAxisMaxIn / kMinWaves; ++t) {
+            const int r = w + nw * t;
             if (r < n_in) sm[r * 64 + lane] = (T)(v[t] - mc);
         }
         __syncthreads();
@@ -249,28 +263,25 @@ __global__ __launch_bounds__(256) void k_axis(const I* __restrict__ in, O* __res
     O* dst = out + (long long)f * n_out * ncol + c0;
     const T mt = (T)m;
     // operator rows are wave-uniform: scalar loads (an LDS copy with
-    // broadcast reads measured 1.9x slower at N_phi = 64)
-    for (int p = 0; p < passes; ++p) {
-        // blocked copy: rows of this wave for input ri at Ww + ri R; circulant:
-        // the sliding window dv[n_in + q0 - ri ...] of a vector that stays in
-        // the scalar cache
-        const T* Ww = CIRC ? Wb + n_in + (p * 4 + w) * R : Wb + (long long)(p * 4 + w) * n_in * R;
-        T acc[R];
+    // broadcast reads measured 1.9x slower at N_phi = 64).  Blocked copy: the
+    // rows of this wave for input ri at Ww + ri R; circulant: the sliding
+    // window dv[n_in + q0 - ri ...] of a vector that stays in the scalar cache
+    const T* Ww = CIRC ? Wb + n_in + w * R : Wb + (long long)w * n_in * R;
+    T acc[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) acc[r] = (T)0;
-        #pragma unroll 4   // operator loads run ahead of the FMAs (measured against 1, 2, default)
-        for (int ri = 0; ri < n_in; ++ri) {
-            const T v = sm[ri * 64 + lane] - mt;   // mt = 0 for FP32 tiles
-            const T* wr = CIRC ? Ww - ri : Ww + ri * R;
+    for (int r = 0; r < R; ++r) acc[r] = (T)0;
+    #pragma unroll 4   // operator loads run ahead of the FMAs (measured against 1, 2, default)
+    for (int ri = 0; ri < n_in; ++ri) {
+        const T v = sm[ri * 64 + lane] - mt;   // mt = 0 for FP32 tiles
+        const T* wr = CIRC ? Ww - ri : Ww + ri * R;
 #pragma unroll
-            for (int r = 0; r < R; ++r) acc[r] = fma(wr[r], v, acc[r]);
-        }
-        if (colok) {
+        for (int r = 0; r < R; ++r) acc[r] = fma(wr[r], v, acc[r]);
+    }
+    if (colok) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int q = (p * 4 + w) * R + r;
-                if (q < n_out) dst[(long long)q * ncol + lane] = (O)acc[r];
-            }
+        for (int r = 0; r < R; ++r) {
+            const int q = w * R + r;
+            if (q < n_out) dst[(long long)q * ncol + lane] = (O)acc[r];
         }
     }
 }
@@ -310,10 +321,14 @@ std::vector<double> block_operator(const std::vector<double>& W, int n_out, int 
     return Wb;
 }
 
-void blocked_shape(int n_out, int& R, int& passes) {
-    const int per = (n_out + 3) / 4;              // rows per wave
-    passes = (per + kMaxRows - 1) / kMaxRows;
-    R = (per + passes - 1) / passes;
+int blocked_shape(int n_out, int target, int& R, int& passes) {
+    int nw = (n_out + target - 1) / target;
+    nw = (nw + 3) / 4 * 4;
+    if (nw < kMinWaves) nw = kMinWaves;
+    if (nw > kMaxWaves) nw = kMaxWaves;
+    R = (n_out + nw - 1) / nw;
+    passes = nw / 4;
+    return R <= kMaxRows ? 0 : -1;
 }
 
 #define SG_R_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) \
@@ -323,8 +338,9 @@ hipError_t launch_dr(const KShell& s, const double* in, double* out, int n_field
     const long long n_lines = (long long)n_fields * s.npts / s.n_r;
     const unsigned blocks = (unsigned)((n_lines + 63) / 64);
     const size_t shm = sizeof(double) * size_t(s.n_r) * kDrStride;
+    const unsigned nt = 64u * s.Dr_nw;
     switch (s.Dr_R) {
-#define X(R) case R: hipLaunchKernelGGL(k_dr<R>, dim3(blocks), dim3(256), shm, st, in, out, s.Drb, s.n_r, n_lines); break;
+#define X(R) case R: hipLaunchKernelGGL(k_dr<R>, dim3(blocks), dim3(nt), shm, st, in, out, s.Drb, s.n_r, n_lines); break;
         SG_R_CASES(X)
 #undef X
         default: return hipErrorInvalidValue;
@@ -337,10 +353,11 @@ static hipError_t dtheta_t(const KShell& s, const double* in, O* out, const T* H
                            hipStream_t st) {
     const long long n_cols = (long long)n_fields * (s.n_ph / 2) * s.n_r;
     const unsigned blocks = (unsigned)((n_cols + 63) / 64);
-    if (s.n_th > 4 * kThMaxPerThread) return hipErrorInvalidValue;
-    const size_t shm = sizeof(T) * 2 * size_t(s.n_th) * 64 + 4 * 64 * sizeof(double);
+    if (s.n_th > s.Hth_nw * kThMaxPerThread) return hipErrorInvalidValue;
+    const size_t shm = sizeof(T) * 2 * size_t(s.n_th) * 64 + size_t(s.Hth_nw) * 64 * sizeof(double);
+    const unsigned nt = 64u * s.Hth_nw;
     switch (s.Hth_R) {
-#define X(R) case R: hipLaunchKernelGGL((k_dtheta<R, T, O>), dim3(blocks), dim3(256), shm, st, in, out, Hsb, Hab, s.n_r, s.n_th, s.n_ph, n_cols); break;
+#define X(R) case R: hipLaunchKernelGGL((k_dtheta<R, T, O>), dim3(blocks), dim3(nt), shm, st, in, out, Hsb, Hab, s.n_r, s.n_th, s.n_ph, n_cols); break;
         SG_R_CASES(X)
 #undef X
         default: return hipErrorInvalidValue;
@@ -359,18 +376,19 @@ hipError_t launch_dtheta_f32(const KShell& s, const double* in, float* out, int 
 template <typename I, typename T, typename O>
 static hipError_t axis_t(const AxisOp& op, const T* Wb, const I* in, O* out, long long ncol, int n_fields,
                          int center, hipStream_t st) {
-    if (op.n_in > kAxisMaxIn) return hipErrorInvalidValue;
+    if (op.n_in > kAxisMaxIn || 4 * op.passes < kMinWaves) return hipErrorInvalidValue;
     const unsigned bx = (unsigned)((ncol + 63) / 64);
-    const size_t shm = sizeof(T) * size_t(op.n_in) * 64 + 4 * 64 * sizeof(double);
+    const size_t shm = sizeof(T) * size_t(op.n_in) * 64 + size_t(4 * op.passes) * 64 * sizeof(double);
+    const unsigned nt = 256u * op.passes;
     switch (op.R) {
-#define X(R)                                                                                                    \
-    case R:                                                                                                     \
-        if (op.circ)                                                                                            \
-            hipLaunchKernelGGL((k_axis<R, I, T, O, true>), dim3(bx, n_fields), dim3(256), shm, st, in, out, Wb, \
-                               op.n_in, op.n_out, op.passes, ncol, center);                                     \
-        else                                                                                                    \
-            hipLaunchKernelGGL((k_axis<R, I, T, O, false>), dim3(bx, n_fields), dim3(256), shm, st, in, out,    \
-                               Wb, op.n_in, op.n_out, op.passes, ncol, center);                                 \
+#define X(R)                                                                                                   \
+    case R:                                                                                                    \
+        if (op.circ)                                                                                           \
+            hipLaunchKernelGGL((k_axis<R, I, T, O, true>), dim3(bx, n_fields), dim3(nt), shm, st, in, out, Wb, \
+                               op.n_in, op.n_out, ncol, center);                                               \
+        else                                                                                                   \
+            hipLaunchKernelGGL((k_axis<R, I, T, O, false>), dim3(bx, n_fields), dim3(nt), shm, st, in, out,    \
+                               Wb, op.n_in, op.n_out, ncol, center);                                           \
         break;
         SG_R_CASES(X)
 #undef X

@@ -18,6 +18,7 @@ struct KShell {
     const double* Hsb;        // H_L + H_R of the folded theta matrix, wave-blocked
     const double* Hab;        // H_L - H_R, wave-blocked
     int Dr_R, Hth_R;          // rows per wave of the blocked d_r / d_theta operators
+    int Dr_nw, Hth_nw;        // waves per workgroup of k_dr / k_dtheta
     const float* Hsb_f;       // FP32 copies for the mixed-precision path
     const float* Hab_f;
     const double* rk;         // radii
@@ -59,8 +60,26 @@ struct AxisOp {
     int circ = 0;
 };
 
-// Largest number of output rows one wave accumulates per pass.
-constexpr int kMaxRows = 20;   // one pass covers N_r <= 80 and N_theta <= 64 (k_dr, k_dtheta have no passes)
+// Largest number of output rows one wave accumulates, and of waves in one
+// workgroup of the derivative kernels (4 kMaxWaves rows cover n <= 320).
+constexpr int kMaxRows = 20;
+constexpr int kMaxWaves = 16, kMinWaves = 8;
+// Target rows per wave: fewer rows means more waves on one staged tile.
+#ifndef SG_DR_ROWS
+#define SG_DR_ROWS 9
+#endif
+#ifndef SG_TH_ROWS
+#define SG_TH_ROWS 8
+#endif
+#ifndef SG_AXIS_ROWS
+#define SG_AXIS_ROWS 8
+#endif
+constexpr int kDrRows = SG_DR_ROWS, kThRows = SG_TH_ROWS, kAxisRows = SG_AXIS_ROWS;
+// Waves per workgroup of the theta filter (Fb is blocked for this many).
+#ifndef SG_FILT_WAVES
+#define SG_FILT_WAVES 8
+#endif
+constexpr int kFiltWaves = SG_FILT_WAVES;
 
 struct ShellHost {
     sg_shell_desc d;
@@ -69,7 +88,7 @@ struct ShellHost {
     int m_keep = 0, K = 0;
     double *Drb = nullptr, *Hsb = nullptr, *Hab = nullptr;
     float *Hsb_f = nullptr, *Hab_f = nullptr;
-    int Dr_R = 0, Hth_R = 0;
+    int Dr_R = 0, Hth_R = 0, Dr_nw = 0, Hth_nw = 0;
     AxisOp dph, ana, syn;                    // d_phi, Fourier analysis, Fourier synthesis
     double *rk = nullptr, *sth = nullptr, *cth = nullptr, *sph = nullptr, *cph = nullptr;
     double *Fb = nullptr;                    // theta filter matrices, FiltPlan layout
@@ -145,7 +164,9 @@ hipError_t launch_axis_f32(const AxisOp& op, const double* in, float* out, long 
 hipError_t launch_axis(const AxisOp& op, const double* in, double* out, long long ncol, int n_fields, int center,
                        hipStream_t st);
 std::vector<double> block_operator(const std::vector<double>& W, int n_out, int n_in, int R, int passes);
-void blocked_shape(int n_out, int& R, int& passes);
+// Rows per wave R and 4-wave groups `passes` (nw = 4 passes waves) for an
+// operator of n_out rows; -1 if R would exceed kMaxRows.
+int blocked_shape(int n_out, int target, int& R, int& passes);
 hipError_t launch_chain(const KShell& s, double* du, int n_fields, hipStream_t st);
 // Kernels taking `count` process a run of `count` identical shells stored one
 // after the other (shell index in blockIdx.y).
