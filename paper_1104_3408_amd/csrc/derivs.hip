@@ -19,7 +19,10 @@
 // R from a target number of rows per wave): more waves per staged tile
 // shorten each wave's load and FMA chains, which bound these kernels when a
 // shell gives only a few workgroups per CU (measured against 4 waves with up
-// to 20 rows each: d_phi 2.02 -> 1.44 ms on 8 shells of 65x64x128).
+// to 20 rows each: d_phi 2.02 -> 1.44 ms on 8 shells of 65x64x128).  Each
+// thread issues all of its tile loads (fully unrolled, in-bounds addresses,
+// unused slots predicated off) before its first LDS store, so a wave waits
+// out one memory latency per tile rather than one per loaded row.
 //
 //   d_r      columns = radial lines (contiguous), tile transposed in LDS;
 //   d_theta  columns = (variable, phi_j with j < N_phi/2, r_k); the two
@@ -47,6 +50,7 @@ __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane
 // is [n_r][65]: the odd row stride keeps the transposing stores and loads of
 // consecutive k (consecutive threads) on different LDS banks.
 constexpr int kDrStride = 65;
+constexpr int kDrPer = (64 * 80 + 64 * kMinWaves - 1) / (64 * kMinWaves);   // tile loads per thread
 
 template <int R>
 __global__ __launch_bounds__(1024) void k_dr(const double* __restrict__ in, double* __restrict__ out,
@@ -60,9 +64,22 @@ __global__ __launch_bounds__(1024) void k_dr(const double* __restrict__ in, doub
     // (e + 1/2)/n_r in FP32 is at least 1/(2 n_r) from an integer and its
     // rounding error (< 1e-5) cannot move the floor
     const float inv_nr = 1.0f / (float)n_r;
-    for (int e = threadIdx.x; e < 64 * n_r; e += blockDim.x) {
-        const int l = (int)(((float)e + 0.5f) * inv_nr), k = e - l * n_r;
-        sm[k * kDrStride + l] = (e < ne) ? src[e] : 0.0;
+    {
+        const int nt = blockDim.x;   // >= 64 kMinWaves, so kDrPer slots cover 64 N_r <= 64 * 80
+        double v[kDrPer];
+#pragma unroll
+        for (int t = 0; t < kDrPer; ++t) {
+            const int e = threadIdx.x + t * nt;
+            v[t] = (e < ne) ? src[e] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < kDrPer; ++t) {
+            const int e = threadIdx.x + t * nt;
+            if (e < 64 * n_r) {
+                const int l = (int)(((float)e + 0.5f) * inv_nr), k = e - l * n_r;
+                sm[k * kDrStride + l] = v[t];
+            }
+        }
     }
     __syncthreads();
     const int lane = threadIdx.x & 63;
@@ -124,54 +141,43 @@ __global__ __launch_bounds__(1024) void k_dtheta(const double* __restrict__ in, 
         f = fj / half;
         jp = (int)(fj - f * half);
     }
-    const double* base = in + f * n_ph * plane + (long long)jp * plane + k;
-    double ms = 0.0;   // circle mean of S (subtracted per lane for FP64 tiles)
-    if (sizeof(T) == 8) {
-        double part = 0.0;
-        for (int ip = w; ip < n_th; ip += nw) {
-            double a = 0.0, b = 0.0;
-            if (cok) {
-                a = base[(long long)ip * n_r];
-                b = base[half * plane + (long long)ip * n_r];
-            }
-            part += a + b;
-            sS[ip * 64 + lane] = (T)(a + b);
-            sA[ip * 64 + lane] = (T)(a - b);
-        }
-        spart[w * 64 + lane] = part;
-        __syncthreads();
-        for (int v = 0; v < nw; ++v) ms += spart[v * 64 + lane];
-        ms /= n_th;
-    } else {
-        double sv[kThMaxPerThread], av[kThMaxPerThread];
-        double part = 0.0;
+    const double* base = in + f * n_ph * plane + (long long)jp * plane + k;   // f = jp = k = 0 past the end
+    // S and A of this thread's rows, then the circle mean of S from the
+    // waves' partial sums; the tile holds S - mean (rounded once to T) and A
+    double sv[kThMaxPerThread], av[kThMaxPerThread];
 #pragma unroll
-        for (int t = 0; t < kThMaxPerThread; ++t) {
-            const int ip = w + nw * t;
-            double a = 0.0, b = 0.0;
-            if (cok && ip < n_th) {
-                a = base[(long long)ip * n_r];
-                b = base[half * plane + (long long)ip * n_r];
-            }
-            sv[t] = a + b;
-            av[t] = a - b;
-            part += sv[t];
+    for (int t = 0; t < kThMaxPerThread; ++t) {
+        const int ip = w + nw * t;
+        double a = 0.0, b = 0.0;
+        if (ip < n_th) {
+            a = base[(long long)ip * n_r];
+            b = base[half * plane + (long long)ip * n_r];
         }
-        spart[w * 64 + lane] = part;
-        __syncthreads();
-        double mc = 0.0;
-        for (int v = 0; v < nw; ++v) mc += spart[v * 64 + lane];
-        mc /= n_th;
-#pragma unroll
-        for (int t = 0; t < kThMaxPerThread; ++t) {
-            const int ip = w + nw * t;
-            if (ip < n_th) {
-                sS[ip * 64 + lane] = (T)(sv[t] - mc);
-                sA[ip * 64 + lane] = (T)av[t];
-            }
-        }
-        __syncthreads();
+        sv[t] = a;
+        av[t] = b;
     }
+    double part = 0.0;
+#pragma unroll
+    for (int t = 0; t < kThMaxPerThread; ++t) {
+        const double a = cok ? sv[t] : 0.0, b = cok ? av[t] : 0.0;
+        sv[t] = a + b;
+        av[t] = a - b;
+        part += sv[t];
+    }
+    spart[w * 64 + lane] = part;
+    __syncthreads();
+    double mc = 0.0;
+    for (int v = 0; v < nw; ++v) mc += spart[v * 64 + lane];
+    mc /= n_th;
+#pragma unroll
+    for (int t = 0; t < kThMaxPerThread; ++t) {
+        const int ip = w + nw * t;
+        if (ip < n_th) {
+            sS[ip * 64 + lane] = (T)(sv[t] - mc);
+            sA[ip * 64 + lane] = (T)av[t];
+        }
+    }
+    __syncthreads();
     const T* Sw = Hsb + (long long)w * n_th * R;
     const T* Aw = Hab + (long long)w * n_th * R;
     T aS[R], aA[R];
@@ -179,7 +185,7 @@ __global__ __launch_bounds__(1024) void k_dtheta(const double* __restrict__ in, 
     for (int r = 0; r < R; ++r) aS[r] = aA[r] = (T)0;
     #pragma unroll 4   // operator loads run ahead of the FMAs (measured against 1, 2, default)
     for (int ip = 0; ip < n_th; ++ip) {
-        const T sv = sS[ip * 64 + lane] - (T)ms, av = sA[ip * 64 + lane];   // ms = 0 for FP32 tiles
+        const T sv = sS[ip * 64 + lane], av = sA[ip * 64 + lane];
         const T* hs = Sw + ip * R;
         const T* ha = Aw + ip * R;
 #pragma unroll
@@ -225,43 +231,32 @@ __global__ __launch_bounds__(1024) void k_axis(const I* __restrict__ in, O* __re
     const int w = wave_id();
     const int nw = blockDim.x >> 6;
     const bool colok = lane < nc;
-    double m = 0.0;
-    if (sizeof(T) == 8 || !center) {
-        double part = 0.0;
-        for (int r = w; r < n_in; r += nw) {
-            const double v = colok ? (double)src[(long long)r * ncol + lane] : 0.0;
-            part += v;
-            sm[r * 64 + lane] = (T)v;
-        }
-        if (center) spart[w * 64 + lane] = part;
-        __syncthreads();
-        if (center) {
-            for (int v = 0; v < nw; ++v) m += spart[v * 64 + lane];
-            m /= n_in;
-        }
-    } else {
-        double v[kAxisMaxIn / kMinWaves];
+    // this thread's rows, then (center) the column mean from the waves'
+    // partial sums; the tile holds value - mean, rounded once to T
+    const int lc = colok ? lane : 0;   // an in-bounds column for every lane
+    double v[kAxisMaxIn / kMinWaves];
+#pragma unroll
+    for (int t = 0; t < kAxisMaxIn / kMinWaves; ++t) {
+        const int r = w + nw * t;
+        v[t] = (r < n_in) ? (double)src[(long long)r * ncol + lc] : 0.0;
+    }
+    double mc = 0.0;
+    if (center) {
         double part = 0.0;
 #pragma unroll
-        for (int t = 0; t < kAxisMaxIn / kMinWaves; ++t) {
-            const int r = w + nw * t;
-            v[t] = (r < n_in && colok) ? (double)src[(long long)r * ncol + lane] : 0.0;
-            part += v[t];
-        }
+        for (int t = 0; t < kAxisMaxIn / kMinWaves; ++t) part += v[t];
         spart[w * 64 + lane] = part;
         __syncthreads();
-        double mc = 0.0;
         for (int q = 0; q < nw; ++q) mc += spart[q * 64 + lane];
         mc /= n_in;
-#pragma unroll
-        for (int t = 0; t < kAxisMaxIn / kMinWaves; ++t) {
-            const int r = w + nw * t;
-            if (r < n_in) sm[r * 64 + lane] = (T)(v[t] - mc);
-        }
-        __syncthreads();
     }
+#pragma unroll
+    for (int t = 0; t < kAxisMaxIn / kMinWaves; ++t) {
+        const int r = w + nw * t;
+        if (r < n_in) sm[r * 64 + lane] = (T)(v[t] - mc);
+    }
+    __syncthreads();
     O* dst = out + (long long)f * n_out * ncol + c0;
-    const T mt = (T)m;
     // operator rows are wave-uniform: scalar loads (an LDS copy with
     // broadcast reads measured 1.9x slower at N_phi = 64).  Blocked copy: the
     // rows of this wave for input ri at Ww + ri R; circulant: the sliding
@@ -272,7 +267,7 @@ __global__ __launch_bounds__(1024) void k_axis(const I* __restrict__ in, O* __re
     for (int r = 0; r < R; ++r) acc[r] = (T)0;
     #pragma unroll 4   // operator loads run ahead of the FMAs (measured against 1, 2, default)
     for (int ri = 0; ri < n_in; ++ri) {
-        const T v = sm[ri * 64 + lane] - mt;   // mt = 0 for FP32 tiles
+        const T v = sm[ri * 64 + lane];
         const T* wr = CIRC ? Ww - ri : Ww + ri * R;
 #pragma unroll
         for (int r = 0; r < R; ++r) acc[r] = fma(wr[r], v, acc[r]);

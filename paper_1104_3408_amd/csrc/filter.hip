@@ -282,6 +282,8 @@ __global__ __launch_bounds__(256) void k_recompose(KShell s, const TI* __restric
     }
 }
 
+constexpr int kFtPer = 64 / kFiltWaves;   // theta rows one thread stages (N_theta <= 64)
+
 // theta filter, spec[c][q][i][k] -> spec2 (q = 0: a_0; 2m-1: a_m; 2m: b_m).
 // Workgroup (column tile, m, column set, shell of the run): the columns of a
 // set are (group, r_k) pairs, one per lane, all real or all complex and all
@@ -350,17 +352,24 @@ __global__ __launch_bounds__(1024) void k_ftheta(int n_r, int n_th, int m_keep, 
             rev0 = !neg;
             rev1 = neg;
         }
+        // all loads of this thread's rows first (x0, x1 point into the
+        // state for every lane; lanes past the end store zeros)
+        T la[kFtPer], lb[kFtPer];
+#pragma unroll
+        for (int t = 0; t < kFtPer; ++t) {
+            const int ip = w + nw * t;
+            la[t] = (ip < n_th) ? x0[ip * (long long)n_r] : (T)0;
+            lb[t] = (ip < n_th && x1) ? x1[ip * (long long)n_r] : (T)0;
+        }
         if (pass > 0) __syncthreads();
-        for (int ip = w; ip < n_th; ip += nw) {
-            T a = (T)0, b = (T)0;
-            if (ok) {
-                const T va = x0[ip * (long long)n_r];
-                const T vb = x1 ? x1[ip * (long long)n_r] : (T)0;
-                a = mix ? va + vb : va;
-                b = mix ? va - vb : vb;
+#pragma unroll
+        for (int t = 0; t < kFtPer; ++t) {
+            const int ip = w + nw * t;
+            if (ip < n_th) {
+                const T va = ok ? la[t] : (T)0, vb = ok ? lb[t] : (T)0;
+                v0[(rev0 ? n_th - 1 - ip : ip) * 64 + lane] = mix ? va + vb : va;
+                v1[(rev1 ? n_th - 1 - ip : ip) * 64 + lane] = mix ? va - vb : vb;
             }
-            v0[(rev0 ? n_th - 1 - ip : ip) * 64 + lane] = a;
-            v1[(rev1 ? n_th - 1 - ip : ip) * 64 + lane] = b;
         }
         __syncthreads();
         T acc0[R], acc1[R];

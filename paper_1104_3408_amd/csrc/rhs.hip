@@ -74,6 +74,12 @@ __global__ __launch_bounds__(kWaves * 64, 2) void k_rhs(KShell s, const double* 
     const long long p0 = (long long)blockIdx.x * kPts;
     const long long p = p0 + lane;
     const bool ok = p < np;
+    // Every global load below uses pc, a point inside the shell for every
+    // lane (lanes past the end read the last point and store nothing), so
+    // that the loads of a phase sit in one basic block with no per-lane
+    // branch and are all in flight before the first wait: the kernel is
+    // bound by how many memory latencies a wave waits out one after another.
+    const long long pc = ok ? p : np - 1;
 
     // ---- per-thread geometry (every thread's point is its lane: the staging
     // loops below step by a multiple of 64) ------------------------------------
@@ -83,22 +89,35 @@ __global__ __launch_bounds__(kWaves * 64, 2) void k_rhs(KShell s, const double* 
     const double st = s.sth[i], ct = s.cth[i], sp = s.sph[j], cp = s.cph[j];
 
     // ---- stage the variables; points past the end get Minkowski data --------
+    {
+        constexpr int kT = (NV + kWaves - 1) / kWaves;
+        double v[kT];
 #pragma unroll
-    for (int t = 0; t < (NV + kWaves - 1) / kWaves; ++t) {
-        const int f = w + t * kWaves;
-        if (f >= NV) break;
-        su[f][lane] = ok ? u[(long long)f * np + p] : ((f == 0) ? -1.0 : ((f == 4 || f == 7 || f == 9) ? 1.0 : 0.0));
+        for (int t = 0; t < kT; ++t) v[t] = u[(long long)min(w + t * kWaves, NV - 1) * np + pc];
+#pragma unroll
+        for (int t = 0; t < kT; ++t) {
+            const int f = w + t * kWaves;
+            if (f < NV) su[f][lane] = ok ? v[t] : ((f == 0) ? -1.0 : ((f == 4 || f == 7 || f == 9) ? 1.0 : 0.0));
+        }
     }
     if (NV == 50) {
-        for (int e = threadIdx.x; e < 16 * kPts; e += kWaves * 64) {
-            const int f = e >> 6, l = e & 63;
-            const long long q = p0 + l;
+        // rows f = w + 4 t of the [16][64] block H_a (f < 4), d_x H_b (f >= 4)
+        double v[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int f = w + 4 * t;
+            v[t] = (f < 4) ? s.H[(long long)f * np + pc] : s.dH[(long long)(f - 4) * np + pc];
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int f = w + 4 * t;
+            const double h = ok ? v[t] : 0.0;
             if (f < 4) {
-                sH[f][l] = (q < np) ? s.H[(long long)f * np + q] : 0.0;
-                sdH[0][f][l] = 0.0;                               // static gauge, eq. gauge
+                sH[f][lane] = h;
+                sdH[0][f][lane] = 0.0;                            // static gauge, eq. gauge
             } else {
                 const int x = (f - 4) >> 2, b = (f - 4) & 3;      // Cartesian d_x H_b
-                sdH[x + 1][b][l] = (q < np) ? s.dH[(long long)(x * 4 + b) * np + q] : 0.0;
+                sdH[x + 1][b][lane] = h;
             }
         }
     }
@@ -131,18 +150,20 @@ __global__ __launch_bounds__(kWaves * 64, 2) void k_rhs(KShell s, const double* 
     }
     const double nu[4] = {ial, -bu[0] * ial, -bu[1] * ial, -bu[2] * ial};
     const double nl0 = -al;   // n_a = (-alpha, 0, 0, 0)
-    // Cartesian derivatives d_x u_mu, x = 0..2, of this thread's point: chain
-    // rule of Sec. 2.2 (eq. dvdx) with the analytic Jacobian d(r, theta,
-    // phi)/d(x, y, z)
-    auto cartd = [&](int mu, double d[3]) {
-        d[0] = d[1] = d[2] = 0.0;
-        if (!ok) return;
-        const long long q = (long long)mu * np + p;
-        const double d0 = du[q], d1 = (double)dang[q], d2 = (double)dang[blk + q];
-        if (cart) {
-            d[0] = d0; d[1] = d1; d[2] = d2;
-        } else {
-            const double ir = 1.0 / s.rk[k], irs = ir / st;
+    // Derivatives of u_mu at this thread's point: load3 issues the three
+    // loads (no wait), tocart forms the Cartesian d_x u_mu, x = 0..2, by the
+    // chain rule of Sec. 2.2 (eq. dvdx) with the analytic Jacobian
+    // d(r, theta, phi)/d(x, y, z)
+    auto load3 = [&](int mu, double d[3]) {
+        const long long q = (long long)mu * np + pc;
+        d[0] = du[q];
+        d[1] = (double)dang[q];
+        d[2] = (double)dang[blk + q];
+    };
+    const double ir = 1.0 / s.rk[k], irs = ir / st;
+    auto tocart = [&](double d[3]) {
+        if (!cart) {
+            const double d0 = d[0], d1 = d[1], d2 = d[2];
             d[0] = st * cp * d0 + ct * cp * ir * d1 - sp * irs * d2;
             d[1] = st * sp * d0 + ct * sp * ir * d1 + cp * irs * d2;
             d[2] = ct * d0 - st * ir * d1;
@@ -158,14 +179,16 @@ __global__ __launch_bounds__(kWaves * 64, 2) void k_rhs(KShell s, const double* 
         }
     } else if (w == 1) {
         if (NV == 58) {
+            double d[4][3];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) load3(50 + b, d[b]);
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 sH[b][lane] = su[50 + b][lane];
                 sdH[0][b][lane] = su[54 + b][lane];              // d_t H_b = Q_b
-                double d[3];
-                cartd(50 + b, d);
+                tocart(d[b]);
 #pragma unroll
-                for (int x = 0; x < 3; ++x) sdH[x + 1][b][lane] = d[x];
+                for (int x = 0; x < 3; ++x) sdH[x + 1][b][lane] = d[b][x];
             }
         }
     } else if (w == 2) {
@@ -229,12 +252,17 @@ __global__ __launch_bounds__(kWaves * 64, 2) void k_rhs(KShell s, const double* 
         constexpr int a = decltype(AC)::value < decltype(BC)::value ? decltype(AC)::value : decltype(BC)::value;
         constexpr int b = decltype(AC)::value < decltype(BC)::value ? decltype(BC)::value : decltype(AC)::value;
         constexpr int q = pr(a, b);
-        // Cartesian derivatives of g_ab, Pi_ab, Phi_xab
+        // Cartesian derivatives of g_ab, Pi_ab, Phi_xab, and the values the
+        // stage update reads (acc, ubase of the five fields): all loads first
         double dg[3], dP[3], dF[3][3];
-        cartd(q, dg);
-        cartd(10 + q, dP);
+        load3(q, dg);
+        load3(10 + q, dP);
 #pragma unroll
-        for (int y = 0; y < 3; ++y) cartd(20 + 10 * y + q, dF[y]);
+        for (int y = 0; y < 3; ++y) load3(20 + 10 * y + q, dF[y]);
+        tocart(dg);
+        tocart(dP);
+#pragma unroll
+        for (int y = 0; y < 3; ++y) tocart(dF[y]);
         double nabH = 0.5 * (sdH[a][b][lane] + sdH[b][a][lane]);
 #pragma unroll
         for (int c = 0; c < 4; ++c) nabH -= sHu[c][lane] * Gam(c, a, b);
@@ -272,6 +300,15 @@ __global__ __launch_bounds__(kWaves * 64, 2) void k_rhs(KShell s, const double* 
 #pragma unroll
             for (int x = 0; x < 3; ++x) rF[x] = xh[x] * inorm * wv;
         }
+        double av[5], bv[5];
+        if (stage >= 2) {
+#pragma unroll
+            for (int m = 0; m < 5; ++m) av[m] = acc[(long long)(q + 10 * m) * np + pc];
+        }
+        if (stage == 2 || stage == 3) {
+#pragma unroll
+            for (int m = 0; m < 5; ++m) bv[m] = ubase[(long long)(q + 10 * m) * np + pc];
+        }
         if (ok) {
             auto emit = [&](int m, double kv) {
                 const int mu = q + 10 * m;
@@ -283,13 +320,13 @@ __global__ __launch_bounds__(kWaves * 64, 2) void k_rhs(KShell s, const double* 
                     acc[o] = u0 + dt * (1.0 / 6.0) * kv;
                     out[o] = u0 + 0.5 * dt * kv;
                 } else if (stage == 2) {        // k2 at us: acc += dt/3 k2, us = u + dt/2 k2
-                    acc[o] = acc[o] + dt * (1.0 / 3.0) * kv;
-                    out[o] = ubase[o] + 0.5 * dt * kv;
+                    acc[o] = av[m] + dt * (1.0 / 3.0) * kv;
+                    out[o] = bv[m] + 0.5 * dt * kv;
                 } else if (stage == 3) {        // k3: acc += dt/3 k3, us = u + dt k3
-                    acc[o] = acc[o] + dt * (1.0 / 3.0) * kv;
-                    out[o] = ubase[o] + dt * kv;
+                    acc[o] = av[m] + dt * (1.0 / 3.0) * kv;
+                    out[o] = bv[m] + dt * kv;
                 } else {                        // k4: u = acc + dt/6 k4
-                    out[o] = acc[o] + dt * (1.0 / 6.0) * kv;
+                    out[o] = av[m] + dt * (1.0 / 6.0) * kv;
                 }
             };
             emit(0, rg);
