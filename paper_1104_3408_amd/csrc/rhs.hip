@@ -246,19 +246,29 @@ __global__ __launch_bounds__(kWaves * 64, 2) void k_rhs(KShell s, const double* 
     __syncthreads();
     const double nC = nu[0] * sC[0][lane] + nu[1] * sC[1][lane] + nu[2] * sC[2][lane] + nu[3] * sC[3][lane];
 
+    // derivative loads of pair q (g_ab, Pi_ab, Phi_xab; no wait)
+    auto load_pair = [&](int q, double (&d)[5][3]) {
+        load3(q, d[0]);
+        load3(10 + q, d[1]);
+#pragma unroll
+        for (int y = 0; y < 3; ++y) load3(20 + 10 * y + q, d[2 + y]);
+    };
     // sources, derivative terms, boundary operator and stage update of pair
-    // (a, b), given its quadratic bracket
-    auto pair_tail = [&](auto AC, auto BC, double quad) {
+    // (a, b), given its quadratic bracket and its loaded derivatives d; the
+    // derivative loads of the wave's next pair (NC >= 0) are issued into dn
+    // together with this pair's stage-update reads, so their latency overlaps
+    // this pair's stores
+    auto pair_tail = [&](auto AC, auto BC, double quad, double (&d)[5][3], auto NC, double (&dn)[5][3]) {
         constexpr int a = decltype(AC)::value < decltype(BC)::value ? decltype(AC)::value : decltype(BC)::value;
         constexpr int b = decltype(AC)::value < decltype(BC)::value ? decltype(BC)::value : decltype(AC)::value;
         constexpr int q = pr(a, b);
-        // Cartesian derivatives of g_ab, Pi_ab, Phi_xab, and the values the
-        // stage update reads (acc, ubase of the five fields): all loads first
-        double dg[3], dP[3], dF[3][3];
-        load3(q, dg);
-        load3(10 + q, dP);
+        double(&dg)[3] = d[0];
+        double(&dP)[3] = d[1];
+        double dF[3][3];
 #pragma unroll
-        for (int y = 0; y < 3; ++y) load3(20 + 10 * y + q, dF[y]);
+        for (int y = 0; y < 3; ++y)
+#pragma unroll
+            for (int x = 0; x < 3; ++x) dF[y][x] = d[2 + y][x];
         tocart(dg);
         tocart(dP);
 #pragma unroll
@@ -309,6 +319,7 @@ __global__ __launch_bounds__(kWaves * 64, 2) void k_rhs(KShell s, const double* 
 #pragma unroll
             for (int m = 0; m < 5; ++m) bv[m] = ubase[(long long)(q + 10 * m) * np + pc];
         }
+        if constexpr (decltype(NC)::value >= 0) load_pair(decltype(NC)::value, dn);
         if (ok) {
             auto emit = [&](int m, double kv) {
                 const int mu = q + 10 * m;
@@ -373,6 +384,10 @@ __global__ __launch_bounds__(kWaves * 64, 2) void k_rhs(KShell s, const double* 
         // Contractions streamed so that few values are live at a time (the
         // register budget decides how many workgroups share a CU): Phi part
         // per spatial x, Pi part per c, Gamma part per column e of G Gamma_b.
+        constexpr int q1 = pr(a1, b), q2 = pr(a2, b), q3 = three ? pr(a3, b) : -1;
+        double dA[5][3], dB[5][3];
+        load_pair(q1, dA);
+        __builtin_amdgcn_sched_barrier(0);
         double quad1 = 0.0, quad2 = 0.0, quad3 = 0.0;
 #pragma unroll
         for (int x = 0; x < 3; ++x) {
@@ -416,15 +431,15 @@ __global__ __launch_bounds__(kWaves * 64, 2) void k_rhs(KShell s, const double* 
                 }
                 }
         }
-        // the barriers keep each pair's derivative loads from being hoisted
-        // above the previous pair (register pressure)
+        // the barriers keep each pair's loads where they are placed
+        // (register pressure)
         __builtin_amdgcn_sched_barrier(0);
-        pair_tail(A1C, BC, quad1);
+        pair_tail(A1C, BC, quad1, dA, PairC<q2>{}, dB);
         __builtin_amdgcn_sched_barrier(0);
-        pair_tail(A2C, BC, quad2);
+        pair_tail(A2C, BC, quad2, dB, PairC<q3>{}, dA);
         if constexpr (three) {
             __builtin_amdgcn_sched_barrier(0);
-            pair_tail(PairC<a3>{}, BC, quad3);
+            pair_tail(PairC<a3>{}, BC, quad3, dA, PairC<-1>{}, dB);
         }
     };
     using None = PairC<-1>;
