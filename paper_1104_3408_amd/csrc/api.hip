@@ -143,9 +143,12 @@ size_t layout_offset(const sg_grid* g, int shell, int nfield) {
     return o;
 }
 
-// The three derivative contractions are independent: with fork (graph
-// capture only) d_theta and d_phi run on the two side streams beside d_r and
-// the stream waits for both, so the captured graph holds three parallel nodes.
+// The three derivative contractions are independent.  They run as one
+// launch (launch_derivs3) whenever their blocked shapes agree on the waves
+// per workgroup and the timing mode is off; otherwise, with fork (graph
+// capture only), d_theta and d_phi run on the two side streams beside d_r
+// and the stream waits for both, so the captured graph holds three parallel
+// nodes.
 static hipError_t fork_begin(sg_grid* g, hipStream_t st) {
     hipError_t e;
     if ((e = hipEventRecord(g->fork_ev[0], st)) != hipSuccess) return e;
@@ -168,6 +171,11 @@ hipError_t derivs_shell(sg_grid* g, int s, const double* in, double* out, int nf
     const KShell v = S.view(nfield);
     const long long cnt = (long long)S.npts * nfield;
     hipError_t e;
+    if (!g->tm.on) {   // one launch for the three (the timing mode keeps them apart, one class each)
+        e = launch_derivs3(v, S.dph, in, out, nfield, st);
+        if (e == hipSuccess) return cart ? launch_chain(v, out, nfield, st) : hipSuccess;
+        if (e != hipErrorNotSupported) return e;
+    }
     if (fork && (e = fork_begin(g, st)) != hipSuccess) return e;
     const hipStream_t s1 = fork ? g->side[0] : st, s2 = fork ? g->side[1] : st;
     {
@@ -197,6 +205,11 @@ hipError_t derivs_shell_mixed(sg_grid* g, int s, const double* in, double* dr, f
     const KShell v = S.view(nfield);
     const long long cnt = (long long)S.npts * nfield;
     hipError_t e;
+    if (!g->tm.on) {
+        e = launch_derivs3_mixed(v, S.dph, in, dr, dang, nfield, st);
+        if (e == hipSuccess) return hipSuccess;
+        if (e != hipErrorNotSupported) return e;
+    }
     if (fork && (e = fork_begin(g, st)) != hipSuccess) return e;
     const hipStream_t s1 = fork ? g->side[0] : st, s2 = fork ? g->side[1] : st;
     {

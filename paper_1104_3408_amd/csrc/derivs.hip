@@ -38,6 +38,8 @@
 //            rounding error of d_phi proportional to sin(theta), so the
 //            1/(r sin theta) of the chain rule does not amplify it) and for
 //            the Fourier analysis/synthesis matrices of the filter (Sec. 3.1).
+#include <algorithm>
+
 #include "internal.h"
 
 namespace sg {
@@ -53,10 +55,10 @@ constexpr int kDrStride = 65;
 constexpr int kDrPer = (64 * 80 + 64 * kMinWaves - 1) / (64 * kMinWaves);   // tile loads per thread
 
 template <int R>
-__global__ __launch_bounds__(1024) void k_dr(const double* __restrict__ in, double* __restrict__ out,
-                                            const double* __restrict__ Db, int n_r, long long n_lines) {
-    extern __shared__ double sm[];   // [n_r][kDrStride]
-    const long long line0 = (long long)blockIdx.x * 64;
+__device__ __forceinline__ void dr_tile(long long tile, const double* __restrict__ in, double* __restrict__ out,
+                                        const double* __restrict__ Db, int n_r, long long n_lines,
+                                        double* __restrict__ sm) {   // sm: [n_r][kDrStride]
+    const long long line0 = tile * 64;
     const int nl = (int)min((long long)64, n_lines - line0);
     const double* src = in + line0 * n_r;
     const int ne = nl * n_r;
@@ -109,6 +111,13 @@ __global__ __launch_bounds__(1024) void k_dr(const double* __restrict__ in, doub
     }
 }
 
+template <int R>
+__global__ __launch_bounds__(1024) void k_dr(const double* __restrict__ in, double* __restrict__ out,
+                                            const double* __restrict__ Db, int n_r, long long n_lines) {
+    extern __shared__ double sm[];
+    dr_tile<R>(blockIdx.x, in, out, Db, n_r, n_lines, sm);
+}
+
 // d_theta on meridian pairs.  Column c = (f * half + jp) * n_r + k; 64
 // columns per workgroup, wave w computes theta rows i = w R + r.  The mean
 // of each meridian circle is removed first (the rows of the Fourier matrix
@@ -116,17 +125,17 @@ __global__ __launch_bounds__(1024) void k_dr(const double* __restrict__ in, doub
 constexpr int kThMaxPerThread = 64 / kMinWaves;   // N_theta <= 64 rows over at least kMinWaves waves
 
 template <int R, typename T, typename O>
-__global__ __launch_bounds__(1024) void k_dtheta(const double* __restrict__ in, O* __restrict__ out,
-                                                const T* __restrict__ Hsb, const T* __restrict__ Hab,
-                                                int n_r, int n_th, int n_ph, long long n_cols) {
-    extern __shared__ double smd[];  // S [n_th][64], A [n_th][64] in T, then partial sums [nw][64] in FP64
+__device__ __forceinline__ void dtheta_tile(long long tile, const double* __restrict__ in, O* __restrict__ out,
+                                            const T* __restrict__ Hsb, const T* __restrict__ Hab, int n_r, int n_th,
+                                            int n_ph, long long n_cols, double* __restrict__ smd) {
+    // smd: S [n_th][64], A [n_th][64] in T, then partial sums [nw][64] in FP64
     T* sm = reinterpret_cast<T*>(smd);
     T* sS = sm;
     T* sA = sm + n_th * 64;
     double* spart = reinterpret_cast<double*>(sm + 2 * n_th * 64);
     const int half = n_ph / 2;
     const long long plane = (long long)n_th * n_r;
-    const long long c0 = (long long)blockIdx.x * 64;
+    const long long c0 = tile * 64;
     // this thread's column; it loads rows ip = w, w + nw, ...
     const int lane = threadIdx.x & 63;
     const int w = wave_id();
@@ -207,6 +216,14 @@ __global__ __launch_bounds__(1024) void k_dtheta(const double* __restrict__ in, 
     }
 }
 
+template <int R, typename T, typename O>
+__global__ __launch_bounds__(1024) void k_dtheta(const double* __restrict__ in, O* __restrict__ out,
+                                                const T* __restrict__ Hsb, const T* __restrict__ Hab,
+                                                int n_r, int n_th, int n_ph, long long n_cols) {
+    extern __shared__ double smd[];
+    dtheta_tile<R, T, O>(blockIdx.x, in, out, Hsb, Hab, n_r, n_th, n_ph, n_cols, smd);
+}
+
 // out[f][q][c] = sum_r W[q][r] (in[f][r][c] - m_c),  m_c = mean of column c
 // over r if center, else 0.  grid: (ceil(ncol/64), n_fields); wave w of nw
 // computes rows q = w R + r.  Thread (w, c) loads rows r = w, w + nw, ... of
@@ -217,15 +234,14 @@ __global__ __launch_bounds__(1024) void k_dtheta(const double* __restrict__ in, 
 constexpr int kAxisMaxIn = 128;
 
 template <int R, typename I, typename T, typename O, bool CIRC>
-__global__ __launch_bounds__(1024) void k_axis(const I* __restrict__ in, O* __restrict__ out,
-                                               const T* __restrict__ Wb, int n_in, int n_out, long long ncol,
-                                               int center) {
-    extern __shared__ double smd[];  // tile [n_in][64] in T, then partial sums [nw][64] in FP64
+__device__ __forceinline__ void axis_tile(long long tile, int f, const I* __restrict__ in, O* __restrict__ out,
+                                          const T* __restrict__ Wb, int n_in, int n_out, long long ncol, int center,
+                                          double* __restrict__ smd) {
+    // smd: tile [n_in][64] in T, then partial sums [nw][64] in FP64
     T* sm = reinterpret_cast<T*>(smd);
     double* spart = reinterpret_cast<double*>(sm + n_in * 64);
-    const long long c0 = (long long)blockIdx.x * 64;
+    const long long c0 = tile * 64;
     const int nc = (int)min((long long)64, ncol - c0);
-    const int f = blockIdx.y;
     const I* src = in + (long long)f * n_in * ncol + c0;
     const int lane = threadIdx.x & 63;
     const int w = wave_id();
@@ -278,6 +294,76 @@ __global__ __launch_bounds__(1024) void k_axis(const I* __restrict__ in, O* __re
             const int q = w * R + r;
             if (q < n_out) dst[(long long)q * ncol + lane] = (O)acc[r];
         }
+    }
+}
+
+template <int R, typename I, typename T, typename O, bool CIRC>
+__global__ __launch_bounds__(1024) void k_axis(const I* __restrict__ in, O* __restrict__ out,
+                                               const T* __restrict__ Wb, int n_in, int n_out, long long ncol,
+                                               int center) {
+    extern __shared__ double smd[];
+    axis_tile<R, I, T, O, CIRC>(blockIdx.x, blockIdx.y, in, out, Wb, n_in, n_out, ncol, center, smd);
+}
+
+// The three coordinate derivatives of one run of shells in one launch:
+// b_dr d_r tiles, b_th d_theta tiles and bx_ph column tiles per field of
+// d_phi, interleaved over the grid so that the three kinds run side by side.
+// Every workgroup has the same number of waves (the host uses this only when
+// the three blocked shapes agree on it).  One launch instead of three on
+// forked streams removes the cross-queue waits of the fork and join (about
+// 20 us per stage at 33x32x64); measured step 0.474 -> 0.464 ms there.
+// Giving each kind of tile its own XCDs (blockIdx mod 8) measured slower.
+// (The array pointers are separate __restrict__ kernel arguments, not struct
+// members: only then may the compiler read the operators through the scalar
+// cache; from a struct they became vector loads and the launch ran 2x slower.)
+struct D3Dims {
+    long long n_lines, n_cols_th, ncol_ph;
+    unsigned b_dr, b_th, bx_ph;
+    int nf;
+    int R_dr, R_th, R_ph;
+    int n_r, n_th, n_ph;
+};
+
+constexpr int kFusedMaxR = 9;   // blocked_shape gives R <= 9 for every operator
+
+template <typename T, typename O>
+__global__ __launch_bounds__(1024) void k_derivs3(const double* __restrict__ in, double* __restrict__ out_r,
+                                                 O* __restrict__ out_th, O* __restrict__ out_ph,
+                                                 const double* __restrict__ Drb, const T* __restrict__ Hsb,
+                                                 const T* __restrict__ Hab, const T* __restrict__ Wph, D3Dims a) {
+    extern __shared__ double smd[];
+    // the three kinds of tiles interleaved evenly over the grid (Bresenham):
+    // block b is the D(b)-th d_r tile if D(b + 1) > D(b), D(b) = floor(b b_dr / B);
+    // otherwise the same rule splits the rest between d_theta and d_phi
+    const unsigned long long B = (unsigned long long)a.b_dr + a.b_th + (unsigned long long)a.bx_ph * a.nf;
+    const unsigned long long bb = blockIdx.x;
+    const unsigned long long d0 = bb * a.b_dr / B, d1 = (bb + 1) * a.b_dr / B;
+    const unsigned long long o = bb - d0, n_o = B - a.b_dr;   // index among the other tiles
+    const unsigned long long t0 = n_o ? o * a.b_th / n_o : 0, t1 = n_o ? (o + 1) * a.b_th / n_o : 0;
+    const bool is_dr = d1 > d0, is_th = !is_dr && t1 > t0;
+    const unsigned long long t_dr = d0, t_th = t0, t_ph = o - t0;
+    if (is_dr) {
+        switch (a.R_dr) {
+#define X(R) case R: dr_tile<R>(t_dr, in, out_r, Drb, a.n_r, a.n_lines, smd); break;
+            X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9)
+#undef X
+        }
+        return;
+    }
+    if (is_th) {
+        switch (a.R_th) {
+#define X(R) case R: dtheta_tile<R, T, O>(t_th, in, out_th, Hsb, Hab, a.n_r, a.n_th, a.n_ph, a.n_cols_th, smd); break;
+            X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9)
+#undef X
+        }
+        return;
+    }
+    const long long bx = (long long)(t_ph % a.bx_ph);
+    const int f = (int)(t_ph / a.bx_ph);
+    switch (a.R_ph) {
+#define X(R) case R: axis_tile<R, double, T, O, true>(bx, f, in, out_ph, Wph, a.n_ph, a.n_ph, a.ncol_ph, 1, smd); break;
+        X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9)
+#undef X
     }
 }
 
@@ -405,6 +491,51 @@ hipError_t launch_axis_f32(const AxisOp& op, const double* in, float* out, long 
 hipError_t launch_axis_ff(const AxisOp& op, const float* in, float* out, long long ncol, int n_fields,
                           hipStream_t st) {
     return axis_t<float, float, float>(op, op.Wb_f, in, out, ncol, n_fields, 0, st);
+}
+
+template <typename T, typename O>
+static hipError_t derivs3_t(const KShell& s, const AxisOp& dph, const T* Wph, const T* Hsb, const T* Hab,
+                            const double* in, double* out_r, O* out_th, O* out_ph, int n_fields, hipStream_t st) {
+    const int nw = s.Dr_nw;
+    if (s.Hth_nw != nw || 4 * dph.passes != nw || !dph.circ || dph.n_in != s.n_ph || s.Dr_R > kFusedMaxR ||
+        s.Hth_R > kFusedMaxR || dph.R > kFusedMaxR)
+        return hipErrorNotSupported;   // shapes disagree: the caller launches the three kernels
+    if (s.n_th > nw * kThMaxPerThread || dph.n_in > kAxisMaxIn) return hipErrorInvalidValue;
+    D3Dims a;
+    a.n_lines = (long long)n_fields * s.npts / s.n_r;
+    a.n_cols_th = (long long)n_fields * (s.n_ph / 2) * s.n_r;
+    a.ncol_ph = (long long)s.n_th * s.n_r;
+    a.b_dr = (unsigned)((a.n_lines + 63) / 64);
+    a.b_th = (unsigned)((a.n_cols_th + 63) / 64);
+    a.bx_ph = (unsigned)((a.ncol_ph + 63) / 64);
+    a.nf = n_fields;
+    a.R_dr = s.Dr_R;
+    a.R_th = s.Hth_R;
+    a.R_ph = dph.R;
+    a.n_r = s.n_r;
+    a.n_th = s.n_th;
+    a.n_ph = s.n_ph;
+    const size_t part = size_t(nw) * 64 * sizeof(double);
+    size_t shm = sizeof(double) * size_t(s.n_r) * kDrStride;
+    shm = std::max(shm, sizeof(T) * 2 * size_t(s.n_th) * 64 + part);
+    shm = std::max(shm, sizeof(T) * size_t(s.n_ph) * 64 + part);
+    const unsigned long long blocks = (unsigned long long)a.b_dr + a.b_th + (unsigned long long)a.bx_ph * n_fields;
+    if (blocks >= (1ull << 31)) return hipErrorNotSupported;
+    hipLaunchKernelGGL((k_derivs3<T, O>), dim3((unsigned)blocks), dim3(64 * nw), shm, st, in, out_r, out_th, out_ph,
+                       s.Drb, Hsb, Hab, Wph, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_derivs3(const KShell& s, const AxisOp& dph, const double* in, double* out, int n_fields,
+                          hipStream_t st) {
+    const long long cnt = (long long)s.npts * n_fields;
+    return derivs3_t<double, double>(s, dph, dph.Wb, s.Hsb, s.Hab, in, out, out + cnt, out + 2 * cnt, n_fields, st);
+}
+
+hipError_t launch_derivs3_mixed(const KShell& s, const AxisOp& dph, const double* in, double* dr, float* dang,
+                                int n_fields, hipStream_t st) {
+    const long long cnt = (long long)s.npts * n_fields;
+    return derivs3_t<float, float>(s, dph, dph.Wb_f, s.Hsb_f, s.Hab_f, in, dr, dang, dang + cnt, n_fields, st);
 }
 
 hipError_t launch_chain(const KShell& s, double* du, int n_fields, hipStream_t st) {

@@ -158,6 +158,13 @@ namespace sg {
 // Launchers (stream-ordered; return a HIP error code).
 hipError_t launch_dr(const KShell& s, const double* in, double* out, int n_fields, hipStream_t st);
 hipError_t launch_dtheta(const KShell& s, const double* in, double* out, int n_fields, hipStream_t st);
+// d_r, d_theta, d_phi of n_fields variables in one launch (out: three blocks
+// of n_fields npts); hipErrorNotSupported when the blocked shapes of the
+// three operators differ in waves per workgroup (nothing is launched then).
+hipError_t launch_derivs3(const KShell& s, const AxisOp& dph, const double* in, double* out, int n_fields,
+                          hipStream_t st);
+hipError_t launch_derivs3_mixed(const KShell& s, const AxisOp& dph, const double* in, double* dr, float* dang,
+                                int n_fields, hipStream_t st);
 hipError_t launch_dtheta_f32(const KShell& s, const double* in, float* out, int n_fields, hipStream_t st);
 hipError_t launch_axis_f32(const AxisOp& op, const double* in, float* out, long long ncol, int n_fields, int center,
                            hipStream_t st);
