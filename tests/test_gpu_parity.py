@@ -210,6 +210,37 @@ def test_graph_replays_match_eager():
     assert float(scratch) == float(scratch)
 
 
+@pytest.mark.parametrize("prec", [ss.SG_PREC_FP64, ss.SG_PREC_FP32])
+@pytest.mark.parametrize("shape", [(13, 8, 16), (33, 32, 64), (17, 16, 32)])
+def test_fused_derivative_launch_matches_separate_launches(shape, prec):
+    """The one-launch form of the three derivative contractions (used by the
+    captured step and by eager calls) runs the same tiles as the three
+    separate launches of the timing mode: identical results, bit for bit,
+    for the derivatives and for filtered steps in both precisions."""
+    n_r, n_th, n_ph = shape
+    g = ss.ShellGrid([(n_r, n_th, n_ph, 1.8, 11.8)], precision=prec)
+    r, th, ph = g.coords(0)
+    g10 = inputs.perturbed_kerr_schild(2, r, th, ph)
+    u0 = torch.zeros(g.state_size, dtype=torch.float64, device="cuda")
+    g.kerr_schild_data(dev(g10.ravel()), u0)
+    if prec == ss.SG_PREC_FP64:
+        d_fused = torch.zeros(3 * g.state_size, dtype=torch.float64, device="cuda")
+        d_sep = torch.zeros_like(d_fused)
+        g.spec_derivs(u0, d_fused)
+        g.enable_timing(True)
+        g.spec_derivs(u0, d_sep)
+        g.enable_timing(False)
+        torch.cuda.synchronize()
+        assert torch.equal(d_fused, d_sep)
+    ua, ub = u0.clone(), u0.clone()
+    g.rk_step(ua, 3)                    # captured graph, fused launches
+    g.enable_timing(True)
+    g.rk_step(ub, 3)                    # eager, three launches per stage
+    g.enable_timing(False)
+    torch.cuda.synchronize()
+    assert torch.isfinite(ua).all() and torch.equal(ua, ub)
+
+
 @pytest.mark.parametrize("shells", [[(13, 8, 16, 1.8, 11.8), (9, 10, 20, 2.5, 8.0)],
                                     [(9, 8, 16, 1.8, 11.8), (9, 8, 16, 1.8, 11.8), (9, 10, 20, 2.5, 8.0),
                                      (9, 10, 20, 2.5, 8.0), (9, 10, 20, 2.5, 8.0)]])
