@@ -311,7 +311,14 @@ def main():
         res["max_rel_diff_vs_fp64_gpu"] = d
         res["speedup_vs_fp64"] = res["value"] / res64["value"]
         var["mixed_fp32_angular"] = res
-        del um, uref, gm, gr
+        del um, gm
+        # angular contractions on the matrix cores from two-part bfloat16
+        # operands (the filter as in the FP32 mode)
+        rb, ub, gb = run_variant(shells, n_v, ss.SG_PREC_BF16X3, args.steps, args.warmup, seed0)
+        rb["max_rel_diff_vs_fp64_gpu"] = (ub - uref).abs().max().item() / uref.abs().max().item()
+        rb["speedup_vs_fp64"] = rb["value"] / res64["value"]
+        var["mixed_bf16x3_angular"] = rb
+        del ub, gb, uref, gr
         for name, steps in (("batch64", 20), ("large8", 10)):
             bshells, bnv = inputs.workload_shells(name)
             bseed = inputs.WORKLOAD_SEED[name]
@@ -322,8 +329,14 @@ def main():
             r32, u32, g32 = run_variant(bshells, bnv, ss.SG_PREC_FP32, steps, 2, bseed)
             r32["max_rel_diff_vs_fp64_gpu"] = (u32 - u64h).abs().max().item() / u64h.abs().max().item()
             r32["speedup_vs_fp64"] = r32["value"] / r64["value"]
-            var[name] = {"shells": len(bshells), "n_fields": bnv, "fp64": r64, "mixed_fp32_angular": r32}
-            del u32, g32, u64h
+            del u32, g32
+            torch.cuda.empty_cache()
+            rb, ub, gb = run_variant(bshells, bnv, ss.SG_PREC_BF16X3, steps, 2, bseed)
+            rb["max_rel_diff_vs_fp64_gpu"] = (ub - u64h).abs().max().item() / u64h.abs().max().item()
+            rb["speedup_vs_fp64"] = rb["value"] / r64["value"]
+            var[name] = {"shells": len(bshells), "n_fields": bnv, "fp64": r64, "mixed_fp32_angular": r32,
+                         "mixed_bf16x3_angular": rb}
+            del ub, gb, u64h
             torch.cuda.empty_cache()
         var["fft_vs_matmul_dphi"] = fft_vs_matmul()
         log("FFT comparison done")

@@ -80,8 +80,13 @@ typedef struct {
                          is split as F(u) = F(u_ref) + F(u - u_ref) with F(u_ref)
                          in FP64 and the difference filtered in FP32 (u_ref: the
                          state at the first rk_step call on that state array);
-                         d_r, the rhs and the RK state stay FP64.  SG_PREC_BF16X3
-                         returns SG_EUNSUPPORTED */
+                         d_r, the rhs and the RK state stay FP64.  SG_PREC_BF16X3:
+                         as SG_PREC_FP32, but the theta and phi contractions run on
+                         the matrix cores with each operand split into two
+                         bfloat16 parts, W x ~ W_hi x_hi + W_hi x_lo + W_lo x_hi
+                         accumulated in FP32 (about 2^-16 of |W||x| per product);
+                         spec_derivs, ghg_rhs and ghg_constraints stay FP64 in
+                         every mode */
     double courant;   /* lambda of Delta t = lambda min(Delta x) (Sec. 4.1), e.g. 4 */
     double mass;      /* black-hole mass M used by sg_kerr_schild_data */
     unsigned flags;   /* SG_CHECK_FINITE: rk_step reports NaN/Inf; SG_NO_GRAPH: rk_step

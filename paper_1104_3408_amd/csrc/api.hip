@@ -95,8 +95,8 @@ sg_status check_opts(const sg_shell_desc* shells, int n_shells, const sg_options
     if (opt->n_fields != 50 && opt->n_fields != 58) return fail(SG_EINVAL, "n_fields must be 50 or 58");
     if (opt->filter_kind < 0 || opt->filter_kind > 3) return fail(SG_EINVAL, "unknown filter_kind");
     if (opt->n_f < 0) return fail(SG_EINVAL, "n_f must be >= 0");
-    if (opt->precision != SG_PREC_FP64 && opt->precision != SG_PREC_FP32)
-        return fail(SG_EUNSUPPORTED, "precision must be SG_PREC_FP64 or SG_PREC_FP32");
+    if (opt->precision != SG_PREC_FP64 && opt->precision != SG_PREC_FP32 && opt->precision != SG_PREC_BF16X3)
+        return fail(SG_EUNSUPPORTED, "precision must be SG_PREC_FP64, SG_PREC_FP32 or SG_PREC_BF16X3");
     if (!(opt->courant > 0)) return fail(SG_EINVAL, "courant must be > 0");
     for (int s = 0; s < n_shells; ++s) {
         const auto& d = shells[s];
@@ -114,6 +114,42 @@ void free_shell(ShellHost& s) {
         if (p) (void)hipFree(p);
     for (float* p : {s.Hsb_f, s.Hab_f, s.dph.Wb_f, s.ana.Wb_f, s.syn.Wb_f, s.Fb_f})
         if (p) (void)hipFree(p);
+    for (uint16_t* p : {s.bf_dph.hi, s.bf_dph.lo, s.bf_hs.hi, s.bf_hs.lo, s.bf_ha.hi, s.bf_ha.lo})
+        if (p) (void)hipFree(p);
+}
+
+// bfloat16 of a float, round to nearest even (raw bits; finite inputs).
+static uint16_t bf16_bits(float x) {
+    uint32_t b;
+    std::memcpy(&b, &x, 4);
+    b += 0x7FFFu + ((b >> 16) & 1u);
+    return (uint16_t)(b >> 16);
+}
+static float bf16_value(uint16_t h) {
+    const uint32_t b = (uint32_t)h << 16;
+    float x;
+    std::memcpy(&x, &b, 4);
+    return x;
+}
+
+// W (n_out x n_in, row-major) split as W = hi + lo in bfloat16 and zero-padded
+// to [M][K] for the matrix-core kernels.
+static hipError_t make_bf3(Bf3Op& op, const std::vector<double>& W, int n_out, int n_in) {
+    op.n_in = n_in;
+    op.n_out = n_out;
+    op.K = (n_in + 15) / 16 * 16;
+    op.M = (n_out + 31) / 32 * 32;
+    std::vector<uint16_t> hi(size_t(op.M) * op.K, 0), lo(size_t(op.M) * op.K, 0);
+    for (int q = 0; q < n_out; ++q)
+        for (int r = 0; r < n_in; ++r) {
+            const float w = (float)W[size_t(q) * n_in + r];
+            const uint16_t h = bf16_bits(w);
+            hi[size_t(q) * op.K + r] = h;
+            lo[size_t(q) * op.K + r] = bf16_bits(w - bf16_value(h));
+        }
+    hipError_t e = upload(&op.hi, hi);
+    if (e != hipSuccess) return e;
+    return upload(&op.lo, lo);
 }
 
 struct TimeScope {
@@ -205,6 +241,23 @@ hipError_t derivs_shell_mixed(sg_grid* g, int s, const double* in, double* dr, f
     const KShell v = S.view(nfield);
     const long long cnt = (long long)S.npts * nfield;
     hipError_t e;
+    if (g->opt.precision == SG_PREC_BF16X3) {   // angular contractions on the matrix cores
+        if (fork && (e = fork_begin(g, st)) != hipSuccess) return e;
+        const hipStream_t s1 = fork ? g->side[0] : st, s2 = fork ? g->side[1] : st;
+        {
+            TimeScope ts(g, SG_K_DR, st);
+            if ((e = launch_dr(v, in, dr, nfield, st)) != hipSuccess) return e;
+        }
+        {
+            TimeScope ts(g, SG_K_DTHETA, s1);
+            if ((e = launch_bf3_dtheta(v, S.bf_hs, S.bf_ha, in, dang, nfield, s1)) != hipSuccess) return e;
+        }
+        {
+            TimeScope ts(g, SG_K_DPHI, s2);
+            if ((e = launch_bf3_dphi(v, S.bf_dph, in, dang + cnt, nfield, s2)) != hipSuccess) return e;
+        }
+        return fork ? fork_end(g, st) : hipSuccess;
+    }
     if (!g->tm.on) {
         e = launch_derivs3_mixed(v, S.dph, in, dr, dang, nfield, st);
         if (e == hipSuccess) return hipSuccess;
@@ -401,6 +454,7 @@ sg_status shell_grid_create(const sg_shell_desc* shells, int n_shells, const sg_
             S.Drb = T.Drb; S.Hsb = T.Hsb; S.Hab = T.Hab; S.Hsb_f = T.Hsb_f; S.Hab_f = T.Hab_f;
             S.Dr_R = T.Dr_R; S.Hth_R = T.Hth_R; S.Dr_nw = T.Dr_nw; S.Hth_nw = T.Hth_nw;
             S.dph = T.dph; S.ana = T.ana; S.syn = T.syn;
+            S.bf_dph = T.bf_dph; S.bf_hs = T.bf_hs; S.bf_ha = T.bf_ha;
             S.rk = T.rk; S.sth = T.sth; S.cth = T.cth; S.sph = T.sph; S.cph = T.cph;
             S.Fb = T.Fb; S.Fb_f = T.Fb_f; S.F_R = T.F_R;
             S.owns_ops = false;
@@ -479,6 +533,14 @@ sg_status shell_grid_create(const sg_shell_desc* shells, int n_shells, const sg_
             upload(&H.cph, cph) != hipSuccess || upload(&H.Fb, fm) != hipSuccess ||
             upload(&H.Fb_f, to_f(fm)) != hipSuccess)
             return cleanup(SG_ENOMEM, "device allocation/upload of operator matrices failed");
+        if (opt->precision == SG_PREC_BF16X3) {
+            std::vector<double> Wph(size_t(np_) * np_);
+            for (int q = 0; q < np_; ++q)
+                for (int c = 0; c < np_; ++c) Wph[size_t(q) * np_ + c] = fd[((q - c) % np_ + np_) % np_];
+            if (make_bf3(H.bf_dph, Wph, np_, np_) != hipSuccess || make_bf3(H.bf_hs, Hs, nt, nt) != hipSuccess ||
+                make_bf3(H.bf_ha, Ha, nt, nt) != hipSuccess)
+                return cleanup(SG_ENOMEM, "upload of the split bfloat16 operators failed");
+        }
     }
     g->total = off;
     g->runs = make_runs(g, nullptr);
@@ -518,7 +580,7 @@ sg_status shell_grid_create(const sg_shell_desc* shells, int n_shells, const sg_
         return cleanup(SG_ENOMEM, "workspace allocation failed");
     if (upload(&g->d_groups, g->groups) != hipSuccess || upload(&g->d_fsets, g->fsets) != hipSuccess)
         return cleanup(SG_ENOMEM, "group upload failed");
-    if (opt->precision == SG_PREC_FP32 && opt->filter_kind != SG_FILTER_NONE) {
+    if (opt->precision != SG_PREC_FP64 && opt->filter_kind != SG_FILTER_NONE) {
         if (hipMalloc((void**)&g->uref, sizeof(double) * g->total) != hipSuccess ||
             hipMalloc((void**)&g->furef, sizeof(double) * g->total) != hipSuccess ||
             hipMalloc((void**)&g->tcol32, sizeof(float) * g->total) != hipSuccess ||
@@ -667,7 +729,7 @@ static hipError_t step_launches(sg_grid* g, double* u, const double* dt, hipStre
         double* ac = g->acc + S.off;
         const double* in[4] = {u0, a, b, a};
         double* outp[4] = {a, b, a, u0};
-        const bool mixed = g->opt.precision == SG_PREC_FP32;
+        const bool mixed = g->opt.precision != SG_PREC_FP64;
         float* dang = reinterpret_cast<float*>(g->dbuf + S.count * R.count);
         for (int stage = 1; stage <= 4; ++stage) {
             if (mixed) {

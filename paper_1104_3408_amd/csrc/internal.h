@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <cstdint>
 #include <string>
 #include <vector>
 
@@ -81,6 +82,15 @@ constexpr int kDrRows = SG_DR_ROWS, kThRows = SG_TH_ROWS, kAxisRows = SG_AXIS_RO
 #endif
 constexpr int kFiltWaves = SG_FILT_WAVES;
 
+// A contraction operator split into two bfloat16 parts (raw bits), W = hi +
+// lo, zero-padded to [M][K] (M a multiple of 32, K of 16) for the matrix
+// cores (SG_PREC_BF16X3).
+struct Bf3Op {
+    uint16_t* hi = nullptr;
+    uint16_t* lo = nullptr;
+    int n_in = 0, n_out = 0, K = 0, M = 0;
+};
+
 struct ShellHost {
     sg_shell_desc d;
     size_t off = 0, count = 0, npts = 0;
@@ -90,6 +100,7 @@ struct ShellHost {
     float *Hsb_f = nullptr, *Hab_f = nullptr;
     int Dr_R = 0, Hth_R = 0, Dr_nw = 0, Hth_nw = 0;
     AxisOp dph, ana, syn;                    // d_phi, Fourier analysis, Fourier synthesis
+    Bf3Op bf_dph, bf_hs, bf_ha;              // split d_phi, H_L + H_R, H_L - H_R (BF16X3 only)
     double *rk = nullptr, *sth = nullptr, *cth = nullptr, *sph = nullptr, *cph = nullptr;
     double *Fb = nullptr;                    // theta filter matrices, FiltPlan layout
     float *Fb_f = nullptr;                   // FP32 copy
@@ -174,6 +185,10 @@ std::vector<double> block_operator(const std::vector<double>& W, int n_out, int 
 // Rows per wave R and 4-wave groups `passes` (nw = 4 passes waves) for an
 // operator of n_out rows; -1 if R would exceed kMaxRows.
 int blocked_shape(int n_out, int target, int& R, int& passes);
+hipError_t launch_bf3_dphi(const KShell& s, const Bf3Op& op, const double* in, float* out, int n_fields,
+                           hipStream_t st);
+hipError_t launch_bf3_dtheta(const KShell& s, const Bf3Op& hs, const Bf3Op& ha, const double* in, float* out,
+                             int n_fields, hipStream_t st);
 hipError_t launch_chain(const KShell& s, double* du, int n_fields, hipStream_t st);
 // Kernels taking `count` process a run of `count` identical shells stored one
 // after the other (shell index in blockIdx.y).

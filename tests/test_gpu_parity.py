@@ -320,17 +320,24 @@ def test_kernel_timing_classes():
     assert all(m > 0 for m in ms)
 
 
-@pytest.mark.parametrize("n_r,n_th,steps,kind", [(13, 12, 5, "Yn"), (49, 48, 1, "Yn"), (13, 12, 5, "Y")])
-def test_mixed_precision_error(n_r, n_th, steps, kind):
+@pytest.mark.parametrize("prec,unit", [(ss.SG_PREC_FP32, 2.0 ** -24), (ss.SG_PREC_BF16X3, 2.0 ** -16)])
+@pytest.mark.parametrize("n_r,n_th,steps,kind", [(13, 12, 5, "Yn"), (49, 48, 1, "Yn"), (13, 12, 5, "Y"),
+                                                 (33, 32, 2, "Yn")])
+def test_mixed_precision_error(n_r, n_th, steps, kind, prec, unit):
     """SG_PREC_FP32: angular derivatives in FP32 and the filter split as
     F(u) = F(u_ref) + F32(u - u_ref) (d_r, rhs and the RK state in FP64),
-    against the FP64 oracle.  Stated bound, relative to max|u|: one FP32
-    rounding unit of the angular operator per step, amplified by the chain
-    rule, steps * dt * 2^-24 * ||D||_inf / (r_min sin theta_0); ||D||_inf is the
+    against the FP64 oracle.  Stated bound, relative to max|u|: one rounding
+    unit of the angular operator per step, amplified by the chain rule,
+    steps * dt * unit * ||D||_inf / (r_min sin theta_0); ||D||_inf is the
     row-sum norm of the Fourier derivative on N_phi = 2 N_theta points (the phi
     matrix and the double-cover theta matrix share it).  The split filter's
-    rounding is relative to |u - u_ref| and adds nothing visible."""
-    g = ss.ShellGrid([(n_r, n_th, 2 * n_th, 1.8, 11.8)], precision=ss.SG_PREC_FP32, filter=kind)
+    rounding is relative to |u - u_ref| and adds nothing visible.
+    SG_PREC_BF16X3: the same with the angular contractions on the matrix
+    cores from two-part bfloat16 operands (W_hi x_hi + W_hi x_lo + W_lo x_hi in
+    FP32); each product then carries at most 3 * 2^-18 of |W||x| (the dropped
+    W_lo x_lo and the two split residuals, each <= 2^-9 * 2^-9), so the unit
+    is 2^-16."""
+    g = ss.ShellGrid([(n_r, n_th, 2 * n_th, 1.8, 11.8)], precision=prec, filter=kind)
     sh = Shell(n_r, n_th, 2 * n_th, 1.8, 11.8)
     g10 = inputs.perturbed_kerr_schild(3, sh.r, sh.theta, sh.phi)
     u = oid.first_order_data(g10, sh)
@@ -347,9 +354,9 @@ def test_mixed_precision_error(n_r, n_th, steps, kind):
     err = rel(got, ref)
     n = 2 * n_th
     d_norm = np.sum(0.5 / np.abs(np.tan(np.pi * np.arange(1, n) / n)))
-    bound = steps * dt * 2.0 ** -24 * d_norm / (1.8 * np.sin(np.pi / (2 * n_th)))
-    print("mixed precision %dx%dx%d after %d steps: max rel err %.3e (bound %.3e)" % (n_r, n_th, n, steps, err,
-                                                                                      bound))
+    bound = steps * dt * unit * d_norm / (1.8 * np.sin(np.pi / (2 * n_th)))
+    print("precision %d %dx%dx%d after %d steps: max rel err %.3e (bound %.3e)" % (prec, n_r, n_th, n, steps, err,
+                                                                                   bound))
     assert err < bound, (err, bound)
     assert err > 1e-13       # really computed in reduced precision
 
