@@ -123,53 +123,96 @@ __device__ __forceinline__ Cx10 sym2_to_cx10(const Sym2& c) {
     return {{c.tt, 0}, {c.tr, 0}, c.tm, conj(c.tm), {c.rr, 0}, c.rm, conj(c.rm), c.mm, conj(c.mm), {c.mmb, 0}};
 }
 
-// Every field of the point is loaded into registers before any arithmetic,
-// so that one wave keeps all its loads in flight at once (with a single
-// thread per point there are few waves per CU, and load phases interleaved
-// with the arithmetic would each wait a full memory latency).  Measured:
-// 25.6 -> 21.9 us for the FP32 difference columns of a 33x32x64 shell; the
-// same change in k_recompose measured slower (its stores need the base
-// values, and the extra registers halve the waves per SIMD).
-constexpr int kMaxFields = 58;
+// Three waves share 64 points: wave 0 decomposes g and Pi (and H_a, Q_a for
+// 58 fields), waves 1 and 2 both decompose the three Phi_x tensors and write
+// the r-row and the m-row of the rank-3 components respectively (their
+// duplicate reads of the 30 Phi fields hit the CU's cache).  Each wave loads
+// all of its fields into registers before any arithmetic, so its loads are
+// in flight together.  Against one thread per point doing everything this
+// triples the waves in flight, which a kernel with one thread per grid point
+// lacks at the metric's size (measured: FP64 decompose 15.7 -> 14.6 us at
+// 33x32x64, 0.87 -> 0.75 ms at 8 x 65x64x128; the same split of k_recompose,
+// four waves each recomputing the rank-3 recombination, measured slower).
+constexpr int kDecParts = 3;
 
 // With uref the columns of u - uref are formed (in FP64, rounded once to TO).
 template <typename TO, bool REF>
-__global__ __launch_bounds__(256) void k_decompose(KShell s, const double* __restrict__ u_,
-                                                   const double* __restrict__ uref, TO* __restrict__ t) {
+__global__ __launch_bounds__(64 * kDecParts) void k_decompose(KShell s, const double* __restrict__ u_,
+                                                             const double* __restrict__ uref, TO* __restrict__ t) {
     const long long np = s.npts;
     const long long so = (long long)blockIdx.y * s.n_v * np;   // shell of a run
     const double* u0 = u_ + so;
     const double* ur = REF ? uref + so : nullptr;
     t += so;
-    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int part = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const long long p = (long long)blockIdx.x * 64 + (threadIdx.x & 63);
     if (p >= np) return;
-    double uv[kMaxFields];
-#pragma unroll
-    for (int f = 0; f < kMaxFields; ++f) uv[f] = (f < s.n_v) ? u0[(long long)f * np + p] : 0.0;
-    if constexpr (REF) {
-        double rv[kMaxFields];
-#pragma unroll
-        for (int f = 0; f < kMaxFields; ++f) rv[f] = (f < s.n_v) ? ur[(long long)f * np + p] : 0.0;
-#pragma unroll
-        for (int f = 0; f < kMaxFields; ++f) uv[f] -= rv[f];
-    }
     const int i = (int)((p / s.n_r) % s.n_th);
     const int j = (int)(p / ((long long)s.n_r * s.n_th));
-    const Tetrad e = make_tetrad(s, i, j);
     auto put = [&](int c, double v) { t[(long long)c * np + p] = (TO)v; };
     auto putc = [&](int c, cx v) { put(c, v.re); put(c + 1, v.im); };
+    if (part == 0) {
+        double uv[20];
 #pragma unroll
-    for (int blk = 0; blk < 2; ++blk) {          // g, Pi
-        double T[4][4];
+        for (int f = 0; f < 20; ++f) uv[f] = u0[(long long)f * np + p];
+        double hq[8];
+        if (s.n_v == 58) {
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+            for (int f = 0; f < 8; ++f) hq[f] = u0[(long long)(50 + f) * np + p];
+        }
+        if constexpr (REF) {
+            double rv[20];
 #pragma unroll
-            for (int b = a; b < 4; ++b) T[a][b] = T[b][a] = uv[10 * blk + pr(a, b)];
-        const Sym2 c = decomp2(T, e);
-        const int o = 10 * blk;
-        put(o + 0, c.tt); put(o + 1, c.tr); put(o + 2, c.rr); put(o + 3, c.mmb);
-        putc(o + 4, c.tm); putc(o + 6, c.rm); putc(o + 8, c.mm);
+            for (int f = 0; f < 20; ++f) rv[f] = ur[(long long)f * np + p];
+#pragma unroll
+            for (int f = 0; f < 20; ++f) uv[f] -= rv[f];
+            if (s.n_v == 58) {
+#pragma unroll
+                for (int f = 0; f < 8; ++f) hq[f] -= ur[(long long)(50 + f) * np + p];
+            }
+        }
+        const Tetrad e = make_tetrad(s, i, j);
+#pragma unroll
+        for (int blk = 0; blk < 2; ++blk) {          // g, Pi
+            double T[4][4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = a; b < 4; ++b) T[a][b] = T[b][a] = uv[10 * blk + pr(a, b)];
+            const Sym2 c = decomp2(T, e);
+            const int o = 10 * blk;
+            put(o + 0, c.tt); put(o + 1, c.tr); put(o + 2, c.rr); put(o + 3, c.mmb);
+            putc(o + 4, c.tm); putc(o + 6, c.rm); putc(o + 8, c.mm);
+        }
+        if (s.n_v == 58) {
+#pragma unroll
+            for (int blk = 0; blk < 2; ++blk) {      // H_a, Q_a
+                const int o = 50 + 4 * blk;
+                const double v0 = hq[4 * blk];
+                double vr = 0.0;
+                cx vm{0, 0};
+#pragma unroll
+                for (int x = 0; x < 3; ++x) {
+                    const double vx = hq[4 * blk + 1 + x];
+                    vr += e.r[x] * vx;
+                    vm = vm + vx * e.m[x];
+                }
+                put(o, v0); put(o + 1, vr); putc(o + 2, vm);
+            }
+        }
+        return;
     }
+    double uv[30];
+#pragma unroll
+    for (int f = 0; f < 30; ++f) uv[f] = u0[(long long)(20 + f) * np + p];
+    if constexpr (REF) {
+        double rv[30];
+#pragma unroll
+        for (int f = 0; f < 30; ++f) rv[f] = ur[(long long)(20 + f) * np + p];
+#pragma unroll
+        for (int f = 0; f < 30; ++f) uv[f] -= rv[f];
+    }
+    const Tetrad e = make_tetrad(s, i, j);
     Sym2 d[3];
 #pragma unroll
     for (int x = 0; x < 3; ++x) {
@@ -177,11 +220,10 @@ __global__ __launch_bounds__(256) void k_decompose(KShell s, const double* __res
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int b = a; b < 4; ++b) T[a][b] = T[b][a] = uv[20 + 10 * x + pr(a, b)];
+            for (int b = a; b < 4; ++b) T[a][b] = T[b][a] = uv[10 * x + pr(a, b)];
         d[x] = decomp2(T, e);
     }
-    // r-row: real-tensor components contracted with rhat
-    {
+    if (part == 1) {   // r-row: real-tensor components contracted with rhat
         double tt = 0, tr = 0, rr = 0, mmb = 0;
         cx tm{0, 0}, rm{0, 0}, mm{0, 0};
         for (int x = 0; x < 3; ++x) {
@@ -190,9 +232,7 @@ __global__ __launch_bounds__(256) void k_decompose(KShell s, const double* __res
         }
         put(20, tt); put(21, tr); put(22, rr); put(23, mmb);
         putc(24, tm); putc(26, rm); putc(28, mm);
-    }
-    // m-row
-    {
+    } else {           // m-row
         cx tt{0, 0}, tr{0, 0}, tm{0, 0}, tmb{0, 0}, rr{0, 0}, rm{0, 0}, rmb{0, 0}, mm{0, 0}, mmb{0, 0}, mbmb{0, 0};
         for (int x = 0; x < 3; ++x) {
             const cx m = e.m[x];
@@ -203,22 +243,6 @@ __global__ __launch_bounds__(256) void k_decompose(KShell s, const double* __res
         }
         putc(30, tt); putc(32, tr); putc(34, tm); putc(36, tmb); putc(38, rr);
         putc(40, rm); putc(42, rmb); putc(44, mm); putc(46, mmb); putc(48, mbmb);
-    }
-    if (s.n_v == 58) {
-#pragma unroll
-        for (int blk = 0; blk < 2; ++blk) {      // H_a, Q_a
-            const int o = 50 + 4 * blk;
-            const double v0 = uv[o];
-            double vr = 0.0;
-            cx vm{0, 0};
-#pragma unroll
-            for (int x = 0; x < 3; ++x) {
-                const double vx = uv[o + 1 + x];
-                vr += e.r[x] * vx;
-                vm = vm + vx * e.m[x];
-            }
-            put(o, v0); put(o + 1, vr); putc(o + 2, vm);
-        }
     }
 }
 
@@ -443,15 +467,15 @@ hipError_t launch_add_base(const float* t, const double* base, double* u, long l
 }
 
 hipError_t launch_decompose(const KShell& s, int count, const double* u, double* t, hipStream_t st) {
-    const dim3 grid((unsigned)((s.npts + 255) / 256), (unsigned)count);
-    hipLaunchKernelGGL((k_decompose<double, false>), grid, dim3(256), 0, st, s, u, (const double*)nullptr, t);
+    const dim3 grid((unsigned)((s.npts + 63) / 64), (unsigned)count);
+    hipLaunchKernelGGL((k_decompose<double, false>), grid, dim3(64 * kDecParts), 0, st, s, u, (const double*)nullptr, t);
     return hipGetLastError();
 }
 
 hipError_t launch_decompose_delta(const KShell& s, int count, const double* u, const double* uref, float* t,
                                   hipStream_t st) {
-    const dim3 grid((unsigned)((s.npts + 255) / 256), (unsigned)count);
-    hipLaunchKernelGGL((k_decompose<float, true>), grid, dim3(256), 0, st, s, u, uref, t);
+    const dim3 grid((unsigned)((s.npts + 63) / 64), (unsigned)count);
+    hipLaunchKernelGGL((k_decompose<float, true>), grid, dim3(64 * kDecParts), 0, st, s, u, uref, t);
     return hipGetLastError();
 }
 
