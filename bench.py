@@ -217,8 +217,8 @@ def main():
                     help="run one device copy of this many MiB (a known-size kernel for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: shells are independent and this build has no multi-GPU path "
-              "(see the sharding note in the design document); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: there is no multi-GPU path (shells are independent and would be "
+              "assigned to GPUs whole, with no exchange during a step); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
