@@ -756,22 +756,29 @@ static hipError_t step_launches(sg_grid* g, double* u, const double* dt, hipStre
     return hipSuccess;
 }
 
-static void drop_graph(sg_grid* g) {
-    if (g->sgraph.exec) (void)hipGraphExecDestroy(g->sgraph.exec);
-    if (g->sgraph.graph) (void)hipGraphDestroy(g->sgraph.graph);
-    g->sgraph = StepGraph();
+static void drop_graph(StepGraph& sg) {
+    if (sg.exec) (void)hipGraphExecDestroy(sg.exec);
+    if (sg.graph) (void)hipGraphDestroy(sg.graph);
+    sg = StepGraph();
 }
 
-// Capture one step on the grid's private stream and instantiate it.
-static sg_status capture_step(sg_grid* g, double* u, const std::vector<double>& dts) {
-    drop_graph(g);
+static void drop_graph(sg_grid* g) {
+    drop_graph(g->sgraph);
+    drop_graph(g->sgraph_k);
+}
+
+// Capture n_steps filtered steps of the state u into sg (private stream; the
+// three derivative contractions as one launch or forked, see derivs_shell).
+static sg_status capture_steps(sg_grid* g, StepGraph& sg, int n_steps, double* u, const std::vector<double>& dts) {
+    drop_graph(sg);
     if (!g->cap) HIP_TRY(hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking));
     for (auto& sd : g->side)
         if (!sd) HIP_TRY(hipStreamCreateWithFlags(&sd, hipStreamNonBlocking));
     for (auto& ev : g->fork_ev)
         if (!ev) HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     HIP_TRY(hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal));
-    const hipError_t e = step_launches(g, u, dts.data(), g->cap, true);
+    hipError_t e = hipSuccess;
+    for (int n = 0; n < n_steps && e == hipSuccess; ++n) e = step_launches(g, u, dts.data(), g->cap, true);
     hipGraph_t graph = nullptr;
     const hipError_t e2 = hipStreamEndCapture(g->cap, &graph);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -784,10 +791,10 @@ static sg_status capture_step(sg_grid* g, double* u, const std::vector<double>& 
         (void)hipGraphDestroy(graph);
         return fail(SG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e3));
     }
-    g->sgraph.graph = graph;
-    g->sgraph.exec = exec;
-    g->sgraph.u = u;
-    g->sgraph.dt = dts;
+    sg.graph = graph;
+    sg.exec = exec;
+    sg.u = u;
+    sg.dt = dts;
     return SG_OK;
 }
 
@@ -815,11 +822,22 @@ sg_status rk_step(sg_grid* g, double* u, const double* dt, int n_steps, sg_strea
     }
     const bool graph = !g->tm.on && !(g->opt.flags & SG_NO_GRAPH) && n_steps > 0;
     if (graph) {
-        if (!g->sgraph.exec || g->sgraph.u != u || g->sgraph.dt != dts) {
-            sg_status s2 = capture_step(g, u, dts);
-            if (s2 != SG_OK) return s2;
+        auto stale = [&](const StepGraph& sg) { return !sg.exec || sg.u != u || sg.dt != dts; };
+        int n = n_steps;
+        if (n >= kGraphSteps) {
+            if (stale(g->sgraph_k)) {
+                sg_status s2 = capture_steps(g, g->sgraph_k, kGraphSteps, u, dts);
+                if (s2 != SG_OK) return s2;
+            }
+            for (; n >= kGraphSteps; n -= kGraphSteps) HIP_TRY(hipGraphLaunch(g->sgraph_k.exec, st));
         }
-        for (int n = 0; n < n_steps; ++n) HIP_TRY(hipGraphLaunch(g->sgraph.exec, st));
+        if (n > 0) {
+            if (stale(g->sgraph)) {
+                sg_status s2 = capture_steps(g, g->sgraph, 1, u, dts);
+                if (s2 != SG_OK) return s2;
+            }
+            for (; n > 0; --n) HIP_TRY(hipGraphLaunch(g->sgraph.exec, st));
+        }
     } else {
         for (int n = 0; n < n_steps; ++n) HIP_TRY(step_launches(g, u, dts.data(), st, false));
     }

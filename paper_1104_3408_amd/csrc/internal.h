@@ -117,6 +117,12 @@ struct Run {
     int first = 0, count = 0;
 };
 
+// Steps per replay of the longer step graph: consecutive replays of one graph
+// leave a gap of several microseconds on the device between the last kernel
+// of one replay and the first of the next, which a graph of several steps
+// pays once per replay.
+constexpr int kGraphSteps = 8;
+
 struct StepGraph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -162,7 +168,8 @@ struct sg_grid {
     hipStream_t cap = nullptr;        // capture stream for the step graph
     hipStream_t side[2] = {nullptr, nullptr};   // forked branches of the captured step
     hipEvent_t fork_ev[3] = {nullptr, nullptr, nullptr};
-    sg::StepGraph sgraph;
+    sg::StepGraph sgraph;            // one filtered step
+    sg::StepGraph sgraph_k;          // kGraphSteps filtered steps
 };
 
 namespace sg {

@@ -211,6 +211,26 @@ def test_graph_replays_match_eager():
 
 
 @pytest.mark.parametrize("prec", [ss.SG_PREC_FP64, ss.SG_PREC_FP32])
+def test_multi_step_graph_matches_eager(prec):
+    """rk_step replays a graph of several steps while enough remain and a
+    one-step graph for the rest (8 + 3 here); the result equals the eager
+    launches bit for bit, also on a second call that reuses both graphs."""
+    _, sh, g10 = _ks_case(13, 8)
+    g = ss.ShellGrid([(13, 8, 16, 1.8, 11.8)], precision=prec)
+    ge = ss.ShellGrid([(13, 8, 16, 1.8, 11.8)], precision=prec, flags=ss.SG_NO_GRAPH)
+    ua = torch.zeros(50 * sh.npts, dtype=torch.float64, device="cuda")
+    ub = torch.zeros_like(ua)
+    g.kerr_schild_data(dev(g10), ua)      # also sets each grid's static gauge
+    ge.kerr_schild_data(dev(g10), ub)
+    assert torch.equal(ua, ub)
+    for it in range(2):
+        g.rk_step(ua, 11)
+        ge.rk_step(ub, 11)
+        torch.cuda.synchronize()
+        assert torch.isfinite(ua).all() and torch.equal(ua, ub), it
+
+
+@pytest.mark.parametrize("prec", [ss.SG_PREC_FP64, ss.SG_PREC_FP32])
 @pytest.mark.parametrize("shape", [(13, 8, 16), (33, 32, 64), (17, 16, 32)])
 def test_fused_derivative_launch_matches_separate_launches(shape, prec):
     """The one-launch form of the three derivative contractions (used by the
