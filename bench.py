@@ -53,7 +53,7 @@ def algorithmic_bytes(cls, n_r, n_th, n_ph, n_v, K):
     return per_fp * fp + extra
 
 
-KERNEL_SOURCES = {"d_r": "derivs.hip", "d_theta": "derivs.hip", "d_phi": "derivs.hip", "rhs_stage": "rhs.hip",
+KERNEL_SOURCES = {"d_r": "tile_dr.h", "d_theta": "derivs.hip", "d_phi": "derivs.hip", "rhs_stage": "rhs.hip",
                   "filter_decompose": "filter.hip", "filter_recompose": "filter.hip", "filter_theta": "filter.hip",
                   "filter_phi_analysis": "derivs.hip", "filter_phi_synthesis": "derivs.hip"}
 

@@ -242,6 +242,11 @@ hipError_t derivs_shell_mixed(sg_grid* g, int s, const double* in, double* dr, f
     const long long cnt = (long long)S.npts * nfield;
     hipError_t e;
     if (g->opt.precision == SG_PREC_BF16X3) {   // angular contractions on the matrix cores
+        if (!g->tm.on) {
+            e = launch_derivs3_bf3(v, S.bf_dph, S.bf_hs, S.bf_ha, in, dr, dang, nfield, st);
+            if (e == hipSuccess) return hipSuccess;
+            if (e != hipErrorNotSupported) return e;
+        }
         if (fork && (e = fork_begin(g, st)) != hipSuccess) return e;
         const hipStream_t s1 = fork ? g->side[0] : st, s2 = fork ? g->side[1] : st;
         {

@@ -20,7 +20,10 @@
 // MFMA 32x32x16 bf16 operand layout (checked on the device): lane l holds
 // A[m = l % 32][k = 8 (l / 32) + i] and B[k = 8 (l / 32) + i][n = l % 32],
 // i < 8; the 16 results are D[8 (i / 4) + 4 (l / 32) + i % 4][l % 32].
+#include <algorithm>
+
 #include "internal.h"
+#include "tile_dr.h"
 
 namespace sg {
 
@@ -61,27 +64,28 @@ __device__ __forceinline__ floatx16 mfma3(floatx16 acc, const __bf16* __restrict
 }
 
 // out[f][q][c] = sum_r W[q][r] (in[f][r][c] - m_c), m_c the mean of column c
-// over r (the d_phi contraction with the phi-circle mean removed).
-// grid (ceil(ncol / 64), n_fields), 256 threads.
-__global__ __launch_bounds__(256) void k_bf3_axis(const double* __restrict__ in, float* __restrict__ out,
-                                                  const __bf16* __restrict__ Whi, const __bf16* __restrict__ Wlo,
-                                                  int n_in, int n_out, int K, int M, long long ncol) {
-    extern __shared__ double smd[];   // partial sums [4][64] FP64, then hi, lo tiles [64][K + kBfPad]
+// over r (the d_phi contraction with the phi-circle mean removed); column
+// tile `tile` of field f, NW waves.
+template <int NW>
+__device__ __forceinline__ void bf3_axis_tile(long long tile, int f, const double* __restrict__ in,
+                                              float* __restrict__ out, const __bf16* __restrict__ Whi,
+                                              const __bf16* __restrict__ Wlo, int n_in, int n_out, int K, int M,
+                                              long long ncol, double* __restrict__ smd) {
+    // smd: partial sums [NW][64] FP64, then hi, lo tiles [64][K + kBfPad]
     double* spart = smd;
     const int ldx = K + kBfPad;
-    __bf16* xhi = reinterpret_cast<__bf16*>(smd + 4 * 64);
+    __bf16* xhi = reinterpret_cast<__bf16*>(smd + NW * 64);
     __bf16* xlo = xhi + 64 * ldx;
-    const long long c0 = (long long)blockIdx.x * 64;
+    const long long c0 = tile * 64;
     const int nc = (int)min((long long)64, ncol - c0);
-    const int f = blockIdx.y;
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lc = lane < nc ? lane : 0;
     const double* src = in + (long long)f * n_in * ncol + c0 + lc;
-    constexpr int kPer = kBfMaxIn / 4;
+    constexpr int kPer = kBfMaxIn / NW;
     double v[kPer];
 #pragma unroll
     for (int t = 0; t < kPer; ++t) {
-        const int r = w + 4 * t;
+        const int r = w + NW * t;
         v[t] = (r < n_in) ? src[(long long)r * ncol] : 0.0;
     }
     double part = 0.0;
@@ -89,10 +93,13 @@ __global__ __launch_bounds__(256) void k_bf3_axis(const double* __restrict__ in,
     for (int t = 0; t < kPer; ++t) part += v[t];
     spart[w * 64 + lane] = part;
     __syncthreads();
-    const double mc = (spart[lane] + spart[64 + lane] + spart[128 + lane] + spart[192 + lane]) / n_in;
+    double mc = 0.0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) mc += spart[q * 64 + lane];
+    mc /= n_in;
 #pragma unroll
     for (int t = 0; t < kPer; ++t) {
-        const int r = w + 4 * t;
+        const int r = w + NW * t;
         if (r < K) {
             __bf16 h = (__bf16)0.0f, l = (__bf16)0.0f;
             if (r < n_in) split_bf16(v[t] - mc, h, l);
@@ -103,7 +110,7 @@ __global__ __launch_bounds__(256) void k_bf3_axis(const double* __restrict__ in,
     __syncthreads();
     const int blocks = (M / 32) * 2;
     float* dst = out + (long long)f * n_out * ncol + c0;
-    for (int b = w; b < blocks; b += 4) {
+    for (int b = w; b < blocks; b += NW) {
         const int mb = b >> 1, nb = b & 1;
         floatx16 acc;
 #pragma unroll
@@ -123,21 +130,23 @@ __global__ __launch_bounds__(256) void k_bf3_axis(const double* __restrict__ in,
 // d_theta on meridian pairs (even/odd form of k_dtheta): column c =
 // (f * half + jp) * n_r + k, S = f(phi_j) + f(phi_j + pi) with its circle
 // mean removed, A = f(phi_j) - f(phi_j + pi); d f(phi_j) = (Hs S + Ha A) / 2,
-// d f(phi_j + pi) = (Hs S - Ha A) / 2.  grid ceil(n_cols / 64), 256 threads.
-__global__ __launch_bounds__(256) void k_bf3_theta(const double* __restrict__ in, float* __restrict__ out,
-                                                   const __bf16* __restrict__ Shi, const __bf16* __restrict__ Slo,
-                                                   const __bf16* __restrict__ Ahi, const __bf16* __restrict__ Alo,
-                                                   int n_r, int n_th, int n_ph, int K, int M, long long n_cols) {
-    extern __shared__ double smd[];   // partial sums [4][64], then S hi, S lo, A hi, A lo tiles [64][K + kBfPad]
+// d f(phi_j + pi) = (Hs S - Ha A) / 2.  Column tile `tile`, NW waves.
+template <int NW>
+__device__ __forceinline__ void bf3_theta_tile(long long tile, const double* __restrict__ in, float* __restrict__ out,
+                                               const __bf16* __restrict__ Shi, const __bf16* __restrict__ Slo,
+                                               const __bf16* __restrict__ Ahi, const __bf16* __restrict__ Alo,
+                                               int n_r, int n_th, int n_ph, int K, int M, long long n_cols,
+                                               double* __restrict__ smd) {
+    // smd: partial sums [NW][64], then S hi, S lo, A hi, A lo tiles [64][K + kBfPad]
     double* spart = smd;
     const int ldx = K + kBfPad;
-    __bf16* shi = reinterpret_cast<__bf16*>(smd + 4 * 64);
+    __bf16* shi = reinterpret_cast<__bf16*>(smd + NW * 64);
     __bf16* slo = shi + 64 * ldx;
     __bf16* ahi = slo + 64 * ldx;
     __bf16* alo = ahi + 64 * ldx;
     const int half = n_ph / 2;
     const long long plane = (long long)n_th * n_r;
-    const long long c0 = (long long)blockIdx.x * 64;
+    const long long c0 = tile * 64;
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     auto decode = [&](long long c, long long& fo, int& jp, int& k) {
         const long long fj = c / n_r;
@@ -151,11 +160,11 @@ __global__ __launch_bounds__(256) void k_bf3_theta(const double* __restrict__ in
     int jp = 0, k = 0;
     if (cok) decode(c, f, jp, k);
     const double* base = in + f * n_ph * plane + (long long)jp * plane + k;
-    constexpr int kPer = 64 / 4;   // N_theta <= 64
+    constexpr int kPer = 64 / NW;   // N_theta <= 64
     double sv[kPer], av[kPer];
 #pragma unroll
     for (int t = 0; t < kPer; ++t) {
-        const int ip = w + 4 * t;
+        const int ip = w + NW * t;
         double a = 0.0, b = 0.0;
         if (ip < n_th) {
             a = base[(long long)ip * n_r];
@@ -169,10 +178,13 @@ __global__ __launch_bounds__(256) void k_bf3_theta(const double* __restrict__ in
     for (int t = 0; t < kPer; ++t) part += sv[t];
     spart[w * 64 + lane] = part;
     __syncthreads();
-    const double mc = (spart[lane] + spart[64 + lane] + spart[128 + lane] + spart[192 + lane]) / n_th;
+    double mc = 0.0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) mc += spart[q * 64 + lane];
+    mc /= n_th;
 #pragma unroll
     for (int t = 0; t < kPer; ++t) {
-        const int ip = w + 4 * t;
+        const int ip = w + NW * t;
         if (ip < K) {
             __bf16 h = (__bf16)0.0f, l = (__bf16)0.0f, h2 = (__bf16)0.0f, l2 = (__bf16)0.0f;
             if (ip < n_th) {
@@ -187,7 +199,7 @@ __global__ __launch_bounds__(256) void k_bf3_theta(const double* __restrict__ in
     }
     __syncthreads();
     const int blocks = (M / 32) * 2;
-    for (int b = w; b < blocks; b += 4) {
+    for (int b = w; b < blocks; b += NW) {
         const int mb = b >> 1, nb = b & 1;
         floatx16 aS, aA;
 #pragma unroll
@@ -212,10 +224,100 @@ __global__ __launch_bounds__(256) void k_bf3_theta(const double* __restrict__ in
     }
 }
 
+__global__ __launch_bounds__(256) void k_bf3_axis(const double* __restrict__ in, float* __restrict__ out,
+                                                  const __bf16* __restrict__ Whi, const __bf16* __restrict__ Wlo,
+                                                  int n_in, int n_out, int K, int M, long long ncol) {
+    extern __shared__ double smd[];
+    bf3_axis_tile<4>(blockIdx.x, blockIdx.y, in, out, Whi, Wlo, n_in, n_out, K, M, ncol, smd);
+}
+
+__global__ __launch_bounds__(256) void k_bf3_theta(const double* __restrict__ in, float* __restrict__ out,
+                                                   const __bf16* __restrict__ Shi, const __bf16* __restrict__ Slo,
+                                                   const __bf16* __restrict__ Ahi, const __bf16* __restrict__ Alo,
+                                                   int n_r, int n_th, int n_ph, int K, int M, long long n_cols) {
+    extern __shared__ double smd[];
+    bf3_theta_tile<4>(blockIdx.x, in, out, Shi, Slo, Ahi, Alo, n_r, n_th, n_ph, K, M, n_cols, smd);
+}
+
+// One launch for a stage's three contractions in SG_PREC_BF16X3 (the FP64
+// d_r tiles and the two matrix-core tiles interleaved over the grid as in the
+// FP64 form; kMinWaves waves per workgroup).  Pointers are separate
+// __restrict__ arguments (the FP64 d_r operator then stays in scalar loads).
+struct B3Dims {
+    long long n_lines, n_cols_th, ncol_ph;
+    unsigned b_dr, b_th, bx_ph;
+    int nf, R_dr, n_r, n_th, n_ph, K_th, M_th, K_ph, M_ph;
+};
+
+__global__ __launch_bounds__(64 * kMinWaves) void k_derivs3_bf3(
+    const double* __restrict__ in, double* __restrict__ out_r, float* __restrict__ out_th,
+    float* __restrict__ out_ph, const double* __restrict__ Drb, const __bf16* __restrict__ Shi,
+    const __bf16* __restrict__ Slo, const __bf16* __restrict__ Ahi, const __bf16* __restrict__ Alo,
+    const __bf16* __restrict__ Phi, const __bf16* __restrict__ Plo, B3Dims a) {
+    extern __shared__ double smd[];
+    const unsigned long long B = (unsigned long long)a.b_dr + a.b_th + (unsigned long long)a.bx_ph * a.nf;
+    const unsigned long long bb = blockIdx.x;
+    const unsigned long long d0 = bb * a.b_dr / B, d1 = (bb + 1) * a.b_dr / B;
+    const unsigned long long o = bb - d0, n_o = B - a.b_dr;
+    const unsigned long long t0 = n_o ? o * a.b_th / n_o : 0, t1 = n_o ? (o + 1) * a.b_th / n_o : 0;
+    if (d1 > d0) {
+        switch (a.R_dr) {
+#define X(R) case R: dr_tile<R>(d0, in, out_r, Drb, a.n_r, a.n_lines, smd); break;
+            X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9)
+#undef X
+        }
+        return;
+    }
+    if (t1 > t0) {
+        bf3_theta_tile<kMinWaves>(t0, in, out_th, Shi, Slo, Ahi, Alo, a.n_r, a.n_th, a.n_ph, a.K_th, a.M_th,
+                                  a.n_cols_th, smd);
+        return;
+    }
+    const unsigned long long p = o - t0;
+    bf3_axis_tile<kMinWaves>((long long)(p % a.bx_ph), (int)(p / a.bx_ph), in, out_ph, Phi, Plo, a.n_ph, a.n_ph,
+                             a.K_ph, a.M_ph, a.ncol_ph, smd);
+}
+
 }  // namespace
 
-size_t bf3_axis_shm(int K) { return 4 * 64 * sizeof(double) + 2 * size_t(64) * (K + kBfPad) * sizeof(__bf16); }
-size_t bf3_theta_shm(int K) { return 4 * 64 * sizeof(double) + 4 * size_t(64) * (K + kBfPad) * sizeof(__bf16); }
+size_t bf3_axis_shm(int K, int nw = 4) { return nw * 64 * sizeof(double) + 2 * size_t(64) * (K + kBfPad) * sizeof(__bf16); }
+size_t bf3_theta_shm(int K, int nw = 4) { return nw * 64 * sizeof(double) + 4 * size_t(64) * (K + kBfPad) * sizeof(__bf16); }
+
+hipError_t launch_derivs3_bf3(const KShell& s, const Bf3Op& dph, const Bf3Op& hs, const Bf3Op& ha, const double* in,
+                              double* dr, float* dang, int n_fields, hipStream_t st) {
+    if (s.Dr_nw != kMinWaves || s.Dr_R > 9) return hipErrorNotSupported;
+    if (s.n_th > 64 || hs.K != ha.K || hs.M != ha.M || hs.K < s.n_th || hs.K % 16 || hs.M % 32 || hs.M > 64 ||
+        dph.n_in > kBfMaxIn || dph.K < dph.n_in || dph.K % 16 || dph.M % 32 || dph.M > 128)
+        return hipErrorInvalidValue;
+    B3Dims a;
+    a.n_lines = (long long)n_fields * s.npts / s.n_r;
+    a.n_cols_th = (long long)n_fields * (s.n_ph / 2) * s.n_r;
+    a.ncol_ph = (long long)s.n_th * s.n_r;
+    a.b_dr = (unsigned)((a.n_lines + 63) / 64);
+    a.b_th = (unsigned)((a.n_cols_th + 63) / 64);
+    a.bx_ph = (unsigned)((a.ncol_ph + 63) / 64);
+    a.nf = n_fields;
+    a.R_dr = s.Dr_R;
+    a.n_r = s.n_r;
+    a.n_th = s.n_th;
+    a.n_ph = s.n_ph;
+    a.K_th = hs.K;
+    a.M_th = hs.M;
+    a.K_ph = dph.K;
+    a.M_ph = dph.M;
+    size_t shm = sizeof(double) * size_t(s.n_r) * kDrStride;
+    shm = std::max(shm, bf3_theta_shm(hs.K, kMinWaves));
+    shm = std::max(shm, bf3_axis_shm(dph.K, kMinWaves));
+    const unsigned long long blocks = (unsigned long long)a.b_dr + a.b_th + (unsigned long long)a.bx_ph * n_fields;
+    if (blocks >= (1ull << 31)) return hipErrorNotSupported;
+    const long long cnt = (long long)s.npts * n_fields;
+    hipLaunchKernelGGL(k_derivs3_bf3, dim3((unsigned)blocks), dim3(64 * kMinWaves), shm, st, in, dr, dang,
+                       dang + cnt, s.Drb, reinterpret_cast<const __bf16*>(hs.hi),
+                       reinterpret_cast<const __bf16*>(hs.lo), reinterpret_cast<const __bf16*>(ha.hi),
+                       reinterpret_cast<const __bf16*>(ha.lo), reinterpret_cast<const __bf16*>(dph.hi),
+                       reinterpret_cast<const __bf16*>(dph.lo), a);
+    return hipGetLastError();
+}
 
 hipError_t launch_bf3_dphi(const KShell& s, const Bf3Op& op, const double* in, float* out, int n_fields,
                            hipStream_t st) {

@@ -196,6 +196,10 @@ hipError_t launch_bf3_dphi(const KShell& s, const Bf3Op& op, const double* in, f
                            hipStream_t st);
 hipError_t launch_bf3_dtheta(const KShell& s, const Bf3Op& hs, const Bf3Op& ha, const double* in, float* out,
                              int n_fields, hipStream_t st);
+// d_r (FP64, into dr) and the BF16x3 d_theta, d_phi (FP32, into dang) in one
+// launch; hipErrorNotSupported (nothing launched) unless d_r uses kMinWaves.
+hipError_t launch_derivs3_bf3(const KShell& s, const Bf3Op& dph, const Bf3Op& hs, const Bf3Op& ha, const double* in,
+                              double* dr, float* dang, int n_fields, hipStream_t st);
 hipError_t launch_chain(const KShell& s, double* du, int n_fields, hipStream_t st);
 // Kernels taking `count` process a run of `count` identical shells stored one
 // after the other (shell index in blockIdx.y).
