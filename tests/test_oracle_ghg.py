@@ -323,3 +323,90 @@ def test_constraint_norms_definition():
     mx_a, rms_a, mx_i, rms_i = ghg.constraint_norms(C_a, C_iab)
     assert (mx_a, mx_i, rms_i) == (2.0, 1.0, 1.0)
     assert rms_a == pytest.approx(np.sqrt(4.0 / 20.0), rel=1e-15)
+
+
+def _damping_case(seed=13):
+    """Kerr-Schild at three points with |x| = 3 (so that n_a = (-alpha, 0) and
+    n^a = (1/alpha, -beta^i/alpha) differ), exact complex-step derivatives,
+    and a gauge source H = -Gamma + h with h a constant (in space and time)
+    offset.  Returns the points, the oracle's rhs and the hand value of the
+    Pi rows, built with sympy from the metric alone."""
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal((3, 3))
+    x = 3.0 * v / np.linalg.norm(v, axis=0)
+    h = rng.standard_normal((4, 3))
+    u = _ks_state(x)
+    du = _cstep(_ks_state, x)
+    H = _ks_gauge(x) + h
+    dH = np.concatenate([np.zeros_like(H)[None], _cstep(_ks_gauge, x)])   # d_a h = 0
+    got = ghg.rhs(u, du, H, dH)
+    # hand value from the printed terms of eq. Pidot.  On the static solution
+    # with exact derivatives every term vanishes except the two that contain
+    # the offset: the damping term alpha (2 delta^c_(a n_b) - g_ab n^c) C_c with
+    # C_c = H_c + Gamma_c = h_c, and -2 alpha nabla_(a H_b), whose change is
+    # +2 alpha g^cd Gamma_cab h_d (nabla_a H_b = d_a H_b - g^cd Gamma_cab H_d).
+    X = sp.symbols('x y z', real=True)
+    r = sp.sqrt(sum(c ** 2 for c in X))
+    l = [1] + [c / r for c in X]
+    eta = sp.diag(-1, 1, 1, 1)
+    gs = sp.Matrix(4, 4, lambda a, b: eta[a, b] + 2 / r * l[a] * l[b])
+    dgs = [[[sp.diff(gs[a, b], X[c]) for b in range(4)] for a in range(4)] for c in range(3)]
+    expect = np.zeros((4, 4, 3))
+    for p in range(3):
+        sub = dict(zip(X, x[:, p]))
+        g = np.array(gs.evalf(subs=sub), dtype=float)
+        D = np.zeros((4, 4, 4))                       # D[c, a, b] = d_c g_ab, d_t g = 0
+        for c in range(3):
+            D[c + 1] = np.array([[float(dgs[c][a][b].evalf(subs=sub)) for b in range(4)] for a in range(4)])
+        gi = np.linalg.inv(g)
+        alpha = 1.0 / np.sqrt(-gi[0, 0])              # g^tt = -1/alpha^2
+        n_low = np.array([-alpha, 0.0, 0.0, 0.0])
+        n_up = gi @ n_low
+        hp = h[:, p]
+        for a in range(4):
+            for b in range(4):
+                Gam_ab = [0.5 * (D[a, b, c] + D[b, a, c] - D[c, a, b]) for c in range(4)]   # Gamma_cab
+                damp = alpha * (hp[a] * n_low[b] + hp[b] * n_low[a] - g[a, b] * (n_up @ hp))
+                nab = 2.0 * alpha * sum(gi[c, d] * Gam_ab[c] * hp[d] for c in range(4) for d in range(4))
+                expect[a, b, p] = damp + nab
+    return x, got, expect, h
+
+
+def test_constraint_damping_term_against_hand_value():
+    """Eq. Pidot's gauge-constraint damping alpha (2 delta^c_(a n_b) - g_ab n^c) C_c,
+    pinned at C_a != 0 (every other pin has C_a = 0): the oracle's Pi rows equal
+    the hand value, and the g and Phi rows stay zero (the offset enters eq. Pidot
+    only)."""
+    x, got, expect, h = _damping_case()
+    g, Pi, Phi, _ = unpack(got)
+    assert np.abs(expect).max() > 0.1
+    assert np.abs(Pi - expect).max() < 1e-12, np.abs(Pi - expect).max()
+    assert np.abs(g).max() < 1e-12 and np.abs(Phi).max() < 1e-12
+
+
+@pytest.mark.parametrize("mistake", ["sign of C_a n_b", "dropped g_ab n^c C_c", "n^b for n_b"])
+def test_constraint_damping_pin_catches_planted_mistakes(monkeypatch, mistake):
+    """Planted mistakes in the damping term (a flipped sign of the
+    delta^c_(a n_b) part, a dropped trace part, the contravariant normal in
+    place of the covariant one) make the hand-value pin fail."""
+    orig = ghg._es
+    orig_dep = ghg.dependent
+
+    def broken(spec, *ops):
+        if mistake == "sign of C_a n_b" and spec == 'a...,b...->ab...':
+            return -orig(spec, *ops)
+        if mistake == "dropped g_ab n^c C_c" and spec == 'c...,c...->...':
+            return 0 * orig(spec, *ops)
+        return orig(spec, *ops)
+
+    def dep_up_for_low(g, Pi, Phi):
+        q = orig_dep(g, Pi, Phi)
+        q = dict(q)
+        q['n_low'] = q['n_up']
+        return q
+    monkeypatch.setattr(ghg, "_es", broken)
+    if mistake == "n^b for n_b":
+        monkeypatch.setattr(ghg, "dependent", dep_up_for_low)
+    x, got, expect, h = _damping_case()
+    Pi = unpack(got)[1]
+    assert np.abs(Pi - expect).max() > 1e-3
