@@ -79,7 +79,8 @@ typedef struct {
                          derivatives are computed and stored in FP32, and the filter
                          is split as F(u) = F(u_ref) + F(u - u_ref) with F(u_ref)
                          in FP64 and the difference filtered in FP32 (u_ref: the
-                         state at the first rk_step call on that state array);
+                         state at the start of each rk_step call, refreshed every
+                         64 steps);
                          d_r, the rhs and the RK state stay FP64.  SG_PREC_BF16X3:
                          as SG_PREC_FP32, but the theta and phi contractions run on
                          the matrix cores with each operand split into two

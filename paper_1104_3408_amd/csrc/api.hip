@@ -200,6 +200,34 @@ static hipError_t fork_end(sg_grid* g, hipStream_t st) {
     return hipStreamWaitEvent(st, g->fork_ev[2], 0);
 }
 
+// The three separate contractions; with fork, d_theta and d_phi go to the
+// two side streams, and the side streams are joined back to st whatever
+// happens after the fork (an error from a launch leaves no side stream
+// joined to a capture that the caller then ends).
+template <class F1, class F2, class F3>
+static hipError_t three_launches(sg_grid* g, hipStream_t st, bool fork, F1 l_dr, F2 l_th, F3 l_ph) {
+    hipError_t e;
+    if (fork && (e = fork_begin(g, st)) != hipSuccess) return e;
+    const hipStream_t s1 = fork ? g->side[0] : st, s2 = fork ? g->side[1] : st;
+    {
+        TimeScope ts(g, SG_K_DR, st);
+        e = l_dr(st);
+    }
+    if (e == hipSuccess) {
+        TimeScope ts(g, SG_K_DTHETA, s1);
+        e = l_th(s1);
+    }
+    if (e == hipSuccess) {
+        TimeScope ts(g, SG_K_DPHI, s2);
+        e = l_ph(s2);
+    }
+    if (fork) {
+        const hipError_t e2 = fork_end(g, st);
+        if (e == hipSuccess) e = e2;
+    }
+    return e;
+}
+
 // Coordinate (or Cartesian) derivatives of n_fields variables of one shell.
 hipError_t derivs_shell(sg_grid* g, int s, const double* in, double* out, int nfield, bool cart, hipStream_t st,
                         bool fork = false) {
@@ -212,25 +240,14 @@ hipError_t derivs_shell(sg_grid* g, int s, const double* in, double* out, int nf
         if (e == hipSuccess) return cart ? launch_chain(v, out, nfield, st) : hipSuccess;
         if (e != hipErrorNotSupported) return e;
     }
-    if (fork && (e = fork_begin(g, st)) != hipSuccess) return e;
-    const hipStream_t s1 = fork ? g->side[0] : st, s2 = fork ? g->side[1] : st;
-    {
-        TimeScope ts(g, SG_K_DR, st);
-        if ((e = launch_dr(v, in, out, nfield, st)) != hipSuccess) return e;
-    }
-    {
-        TimeScope ts(g, SG_K_DTHETA, s1);
-        if ((e = launch_dtheta(v, in, out + cnt, nfield, s1)) != hipSuccess) return e;
-    }
-    {
-        TimeScope ts(g, SG_K_DPHI, s2);
-        if ((e = launch_axis(S.dph, in, out + 2 * cnt, (long long)S.d.n_theta * S.d.n_r, nfield, 1, s2)) !=
-            hipSuccess)
-            return e;
-    }
-    if (fork && (e = fork_end(g, st)) != hipSuccess) return e;
-    if (cart) return launch_chain(v, out, nfield, st);
-    return hipSuccess;
+    e = three_launches(
+        g, st, fork, [&](hipStream_t q) { return launch_dr(v, in, out, nfield, q); },
+        [&](hipStream_t q) { return launch_dtheta(v, in, out + cnt, nfield, q); },
+        [&](hipStream_t q) {
+            return launch_axis(S.dph, in, out + 2 * cnt, (long long)S.d.n_theta * S.d.n_r, nfield, 1, q);
+        });
+    if (e != hipSuccess) return e;
+    return cart ? launch_chain(v, out, nfield, st) : hipSuccess;
 }
 
 // Mixed precision: d_r in FP64 into dr; d_theta, d_phi in FP32 into dang
@@ -241,51 +258,25 @@ hipError_t derivs_shell_mixed(sg_grid* g, int s, const double* in, double* dr, f
     const KShell v = S.view(nfield);
     const long long cnt = (long long)S.npts * nfield;
     hipError_t e;
+    auto l_dr = [&](hipStream_t q) { return launch_dr(v, in, dr, nfield, q); };
     if (g->opt.precision == SG_PREC_BF16X3) {   // angular contractions on the matrix cores
         if (!g->tm.on) {
             e = launch_derivs3_bf3(v, S.bf_dph, S.bf_hs, S.bf_ha, in, dr, dang, nfield, st);
-            if (e == hipSuccess) return hipSuccess;
             if (e != hipErrorNotSupported) return e;
         }
-        if (fork && (e = fork_begin(g, st)) != hipSuccess) return e;
-        const hipStream_t s1 = fork ? g->side[0] : st, s2 = fork ? g->side[1] : st;
-        {
-            TimeScope ts(g, SG_K_DR, st);
-            if ((e = launch_dr(v, in, dr, nfield, st)) != hipSuccess) return e;
-        }
-        {
-            TimeScope ts(g, SG_K_DTHETA, s1);
-            if ((e = launch_bf3_dtheta(v, S.bf_hs, S.bf_ha, in, dang, nfield, s1)) != hipSuccess) return e;
-        }
-        {
-            TimeScope ts(g, SG_K_DPHI, s2);
-            if ((e = launch_bf3_dphi(v, S.bf_dph, in, dang + cnt, nfield, s2)) != hipSuccess) return e;
-        }
-        return fork ? fork_end(g, st) : hipSuccess;
+        return three_launches(
+            g, st, fork, l_dr, [&](hipStream_t q) { return launch_bf3_dtheta(v, S.bf_hs, S.bf_ha, in, dang, nfield, q); },
+            [&](hipStream_t q) { return launch_bf3_dphi(v, S.bf_dph, in, dang + cnt, nfield, q); });
     }
     if (!g->tm.on) {
         e = launch_derivs3_mixed(v, S.dph, in, dr, dang, nfield, st);
-        if (e == hipSuccess) return hipSuccess;
         if (e != hipErrorNotSupported) return e;
     }
-    if (fork && (e = fork_begin(g, st)) != hipSuccess) return e;
-    const hipStream_t s1 = fork ? g->side[0] : st, s2 = fork ? g->side[1] : st;
-    {
-        TimeScope ts(g, SG_K_DR, st);
-        if ((e = launch_dr(v, in, dr, nfield, st)) != hipSuccess) return e;
-    }
-    {
-        TimeScope ts(g, SG_K_DTHETA, s1);
-        if ((e = launch_dtheta_f32(v, in, dang, nfield, s1)) != hipSuccess) return e;
-    }
-    {
-        TimeScope ts(g, SG_K_DPHI, s2);
-        if ((e = launch_axis_f32(S.dph, in, dang + cnt, (long long)S.d.n_theta * S.d.n_r, nfield, 1, s2)) !=
-            hipSuccess)
-            return e;
-    }
-    if (fork && (e = fork_end(g, st)) != hipSuccess) return e;
-    return hipSuccess;
+    return three_launches(
+        g, st, fork, l_dr, [&](hipStream_t q) { return launch_dtheta_f32(v, in, dang, nfield, q); },
+        [&](hipStream_t q) {
+            return launch_axis_f32(S.dph, in, dang + cnt, (long long)S.d.n_theta * S.d.n_r, nfield, 1, q);
+        });
 }
 
 // Filter of a run of identical shells (state of the run at u).
@@ -322,9 +313,10 @@ hipError_t filter_run(sg_grid* g, const Run& R, double* u, hipStream_t st) {
 }
 
 // Mixed-precision filter of a run by reference splitting: the filter is
-// linear, so F(u) = F(uref) + F(u - uref) with F(uref) formed in FP64 once per
-// rk_step call (furef) and F(u - uref) in FP32 (the difference is small, so
-// its FP32 rounding is small in absolute terms).
+// linear, so F(u) = F(uref) + F(u - uref) with F(uref) formed in FP64 (furef)
+// at the start of every rk_step call and every kRefSteps steps after, and
+// F(u - uref) in FP32 (the difference is small, so its FP32 rounding is small
+// in absolute terms).
 hipError_t filter_run_split(sg_grid* g, const Run& R, double* u, hipStream_t st) {
     const ShellHost& S = g->sh[R.first];
     const KShell v = S.view(g->opt.n_fields);
@@ -557,6 +549,7 @@ sg_status shell_grid_create(const sg_shell_desc* shells, int n_shells, const sg_
         spec = std::max(spec, size_t(R.count) * g->n_cols * S.K * S.d.n_theta * S.d.n_r);
     }
     g->spec_size = spec;
+    g->tcol_size = maxc;
     size_t max_cblocks = 1;
     for (const ShellHost& S : g->sh) max_cblocks = std::max(max_cblocks, (S.npts + 255) / 256);
     if (opt->n_fields == 50) {
@@ -716,6 +709,17 @@ sg_status ghg_rhs(sg_grid* g, const double* u, const double* du_cart, double* rh
     return SG_OK;
 }
 
+// Host-side check that a run's slices of the state and of every workspace the
+// step uses lie inside the grid's allocations (the run's shells are
+// consecutive and identical, so they occupy S.count * R.count doubles).
+static bool run_fits(const sg_grid* g, const Run& R) {
+    if (R.first < 0 || R.count < 1 || R.first + R.count > (int)g->sh.size()) return false;
+    const ShellHost& S = g->sh[R.first];
+    const size_t n = S.count * size_t(R.count);
+    const size_t spec = size_t(R.count) * g->n_cols * S.K * S.d.n_theta * S.d.n_r;
+    return S.off + n <= g->total && n <= g->tcol_size && spec <= g->spec_size;
+}
+
 // One filtered RK4 step of every shell (Sec. 2.5): stage inputs u -> a -> b -> a,
 // the fourth stage writes u; then the filter.
 static hipError_t step_launches(sg_grid* g, double* u, const double* dt, hipStream_t st, bool fork) {
@@ -727,6 +731,7 @@ static hipError_t step_launches(sg_grid* g, double* u, const double* dt, hipStre
         const ShellHost& S = g->sh[R.first];
         const KShell v = S.view(nv);
         const double h = dt[R.first];
+        if (!run_fits(g, R)) return hipErrorInvalidValue;
         const int nvr = nv * R.count;                 // variables of the whole run
         double* u0 = u + S.off;
         double* a = usA + S.off;
@@ -817,18 +822,30 @@ sg_status rk_step(sg_grid* g, double* u, const double* dt, int n_steps, sg_strea
         dts[s] = dt ? dt[s] : g->sh[s].dt;
         if (!(dts[s] > 0.0) || !std::isfinite(dts[s])) return fail(SG_EINVAL, "dt must be finite and positive");
     }
-    if (g->uref && n_steps > 0 && g->ref_of != u) {
-        // mixed precision: the split filter's reference is the state of the
-        // first rk_step call on this state array; F(uref) in FP64
+    // mixed precision: the split filter's reference u_ref is the state at the
+    // start of this call, refreshed every kRefSteps steps (F(u_ref) in FP64),
+    // so the FP32 part always rounds relative to the change of the state over
+    // at most kRefSteps steps, whatever the caller wrote into u before
+    auto refresh_ref = [&]() -> sg_status {
         HIP_TRY(hipMemcpyAsync(g->uref, u, sizeof(double) * g->total, hipMemcpyDeviceToDevice, st));
         HIP_TRY(hipMemcpyAsync(g->furef, u, sizeof(double) * g->total, hipMemcpyDeviceToDevice, st));
         for (const Run& R : g->runs) HIP_TRY(filter_run(g, R, g->furef + g->sh[R.first].off, st));
-        g->ref_of = u;
-    }
+        return SG_OK;
+    };
     const bool graph = !g->tm.on && !(g->opt.flags & SG_NO_GRAPH) && n_steps > 0;
-    if (graph) {
-        auto stale = [&](const StepGraph& sg) { return !sg.exec || sg.u != u || sg.dt != dts; };
-        int n = n_steps;
+    auto stale = [&](const StepGraph& sg) { return !sg.exec || sg.u != u || sg.dt != dts; };
+    for (int done = 0; done < n_steps;) {
+        int n = n_steps - done;
+        if (g->uref) {
+            n = std::min(n, kRefSteps);
+            sg_status s2 = refresh_ref();
+            if (s2 != SG_OK) return s2;
+        }
+        done += n;
+        if (!graph) {
+            for (; n > 0; --n) HIP_TRY(step_launches(g, u, dts.data(), st, false));
+            continue;
+        }
         if (n >= kGraphSteps) {
             if (stale(g->sgraph_k)) {
                 sg_status s2 = capture_steps(g, g->sgraph_k, kGraphSteps, u, dts);
@@ -843,8 +860,6 @@ sg_status rk_step(sg_grid* g, double* u, const double* dt, int n_steps, sg_strea
             }
             for (; n > 0; --n) HIP_TRY(hipGraphLaunch(g->sgraph.exec, st));
         }
-    } else {
-        for (int n = 0; n < n_steps; ++n) HIP_TRY(step_launches(g, u, dts.data(), st, false));
     }
     if (g->opt.flags & SG_CHECK_FINITE) {
         HIP_TRY(hipMemsetAsync(g->d_flag, 0, sizeof(int), st));

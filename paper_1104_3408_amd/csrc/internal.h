@@ -123,6 +123,11 @@ struct Run {
 // pays once per replay.
 constexpr int kGraphSteps = 8;
 
+// Mixed precision: steps between refreshes of the split filter's reference
+// state (the FP32 part of the filter rounds relative to the change of the
+// state since the last refresh; a refresh costs one FP64 filter).
+constexpr int kRefSteps = 64;
+
 struct StepGraph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -156,14 +161,13 @@ struct sg_grid {
     bool tetrad = false;              // Yn: decompose on the tetrad
     double *us = nullptr, *acc = nullptr, *dbuf = nullptr;   // RK and derivative workspaces
     double *tcol = nullptr, *spec = nullptr, *spec2 = nullptr;  // filter workspaces
-    size_t spec_size = 0;
+    size_t spec_size = 0, tcol_size = 0;   // doubles in spec (and spec2), in tcol
     int* d_flag = nullptr;
     double* cpart = nullptr;          // constraint-norm partials, 4 per 256 points of the largest shell
     // mixed-precision filter (SG_PREC_FP32): reference state, its FP64 filter,
     // FP32 column and spectral workspaces
     double *uref = nullptr, *furef = nullptr;
     float *tcol32 = nullptr, *spec32 = nullptr, *spec2_32 = nullptr;
-    const double* ref_of = nullptr;   // state array the reference was taken from
     sg::Timing tm;
     hipStream_t cap = nullptr;        // capture stream for the step graph
     hipStream_t side[2] = {nullptr, nullptr};   // forked branches of the captured step
@@ -229,4 +233,6 @@ hipError_t launch_finite_check(const double* u, size_t n, int* flag, hipStream_t
 // part: ceil(npts/256) * 4 doubles of workspace; norms: 4 doubles.
 hipError_t launch_constraints(const KShell& s, const double* u, const double* dg, double* part, double* norms,
                               hipStream_t st);
+// norms (4 doubles) from the constraint partials of one shell.
+hipError_t launch_constraint_norms(const KShell& s, const double* part, double* norms, hipStream_t st);
 }  // namespace sg

@@ -8,6 +8,7 @@
 // eq. Pidot for a pair need only rows a and b.  The work of a grid point is
 // therefore split by pair across the waves of a workgroup (see k_rhs).
 #include "internal.h"
+#include "constraints.h"
 
 namespace sg {
 
@@ -512,10 +513,9 @@ __global__ __launch_bounds__(256) void k_initial(KShell s, const double* __restr
 }
 
 // Constraint fields of App. A.1 at every point of a shell, reduced per
-// workgroup: C_a = H_a + Gamma_a (Gamma_a = g^bc Gamma_abc, d_t g from eq.
-// gdot) and C_iab = d_i g_ab - Phi_iab with d_i g_ab the Cartesian spectral
-// derivative dg[i][pair][point].  part[blk][4] = (max |C_a|, sum C_a^2,
-// max |C_iab|, sum C_iab^2) over the workgroup's points.
+// workgroup: C_a = H_a + Gamma_a and C_iab = d_i g_ab - Phi_iab with d_i g_ab
+// the Cartesian spectral derivative dg[i][pair][point].  part[blk][4] =
+// (max |C_a|, sum C_a^2, max |C_iab|, sum C_iab^2) over the workgroup's points.
 __global__ __launch_bounds__(256) void k_constraints(KShell s, const double* __restrict__ u,
                                                      const double* __restrict__ dg, double* __restrict__ part) {
     __shared__ double red[4][256];
@@ -523,58 +523,7 @@ __global__ __launch_bounds__(256) void k_constraints(KShell s, const double* __r
     const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
     double mxa = 0.0, ssa = 0.0, mxi = 0.0, ssi = 0.0;
     if (p < np) {
-        double g[4][4], Pi[4][4], F[3][4][4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = a; b < 4; ++b) {
-                const int q = pr(a, b);
-                g[a][b] = g[b][a] = u[q * np + p];
-                Pi[a][b] = Pi[b][a] = u[(10 + q) * np + p];
-#pragma unroll
-                for (int x = 0; x < 3; ++x) F[x][a][b] = F[x][b][a] = u[(20 + 10 * x + q) * np + p];
-            }
-        const double gxx = g[1][1], gxy = g[1][2], gxz = g[1][3], gyy = g[2][2], gyz = g[2][3], gzz = g[3][3];
-        const double cxx = gyy * gzz - gyz * gyz, cxy = gxz * gyz - gxy * gzz, cxz = gxy * gyz - gxz * gyy;
-        const double cyy = gxx * gzz - gxz * gxz, cyz = gxy * gxz - gxx * gyz, czz = gxx * gyy - gxy * gxy;
-        const double idet = 1.0 / (gxx * cxx + gxy * cxy + gxz * cxz);
-        const double gi[3][3] = {{cxx * idet, cxy * idet, cxz * idet},
-                                 {cxy * idet, cyy * idet, cyz * idet},
-                                 {cxz * idet, cyz * idet, czz * idet}};
-        double bu[3];
-#pragma unroll
-        for (int x = 0; x < 3; ++x) bu[x] = gi[x][0] * g[0][1] + gi[x][1] * g[0][2] + gi[x][2] * g[0][3];
-        const double al = sqrt(bu[0] * g[0][1] + bu[1] * g[0][2] + bu[2] * g[0][3] - g[0][0]);
-        const double ial2 = 1.0 / (al * al);
-        double gI[4][4];
-        gI[0][0] = -ial2;
-#pragma unroll
-        for (int x = 0; x < 3; ++x) {
-            gI[0][x + 1] = gI[x + 1][0] = bu[x] * ial2;
-#pragma unroll
-            for (int y = 0; y < 3; ++y) gI[x + 1][y + 1] = gi[x][y] - bu[x] * bu[y] * ial2;
-        }
-        double D[4][4][4];   // D[c][a][b] = d_c g_ab
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                D[0][a][b] = -al * Pi[a][b] + bu[0] * F[0][a][b] + bu[1] * F[1][a][b] + bu[2] * F[2][a][b];
-#pragma unroll
-                for (int x = 0; x < 3; ++x) D[x + 1][a][b] = F[x][a][b];
-            }
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            double t = 0.0;
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) t += gI[a][b] * 0.5 * (D[a][b][c] + D[b][a][c] - D[c][a][b]);
-            const double h = s.n_v == 58 ? u[(50 + c) * np + p] : s.H[c * np + p];
-            const double ca = h + t;
-            mxa = fmax(mxa, fabs(ca));
-            ssa += ca * ca;
-        }
+        gauge_constraint(s, u, p, mxa, ssa);
 #pragma unroll
         for (int x = 0; x < 3; ++x)
 #pragma unroll
@@ -584,20 +533,7 @@ __global__ __launch_bounds__(256) void k_constraints(KShell s, const double* __r
                 ssi += ci * ci;
             }
     }
-    red[0][threadIdx.x] = mxa;
-    red[1][threadIdx.x] = ssa;
-    red[2][threadIdx.x] = mxi;
-    red[3][threadIdx.x] = ssi;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) {
-            red[0][threadIdx.x] = fmax(red[0][threadIdx.x], red[0][threadIdx.x + h]);
-            red[1][threadIdx.x] += red[1][threadIdx.x + h];
-            red[2][threadIdx.x] = fmax(red[2][threadIdx.x], red[2][threadIdx.x + h]);
-            red[3][threadIdx.x] += red[3][threadIdx.x + h];
-        }
-        __syncthreads();
-    }
+    reduce4(red, mxa, ssa, mxi, ssi);
     if (threadIdx.x < 4) part[(long long)blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x][0];
 }
 
@@ -682,6 +618,11 @@ hipError_t launch_constraints(const KShell& s, const double* u, const double* dg
     hipLaunchKernelGGL(k_constraints, dim3(blocks), dim3(256), 0, st, s, u, dg, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    return launch_constraint_norms(s, part, norms, st);
+}
+
+hipError_t launch_constraint_norms(const KShell& s, const double* part, double* norms, hipStream_t st) {
+    const unsigned blocks = (unsigned)((s.npts + 255) / 256);
     hipLaunchKernelGGL(k_constraint_norms, dim3(1), dim3(256), 0, st, part, (int)blocks, (long long)s.npts, norms);
     return hipGetLastError();
 }
