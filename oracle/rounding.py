@@ -1,10 +1,10 @@
-"""Rounding model of the library's reduced-precision angular contractions
-(test helper; CPU, numpy).
+"""Reduced-precision forms of the oracle's angular derivative products
+(oracle; test infrastructure only).
 
-The exact FP64 steps come from the oracle; this module replaces only the two
-angular derivative products of the oracle's right-hand side by the same
-products carried out in reduced precision, so that the error a precision mode
-must show can be predicted on the CPU:
+The exact FP64 steps are the oracle's own; this module replaces only the two
+angular derivative products of the right-hand side (Sec. 2.4 eqs. D2, D3) by
+the same products carried out in the rounding each precision mode defines,
+so that the error a mode must show is predicted on the CPU:
 
   fp32   operator and (mean-removed) input rounded to FP32, products
          accumulated in FP32, result stored in FP32;
@@ -32,9 +32,10 @@ the modes apart: their predictions differ by factors of 100 and more).
 """
 import numpy as np
 
-from oracle import derivs as od
-from oracle.evolve import Evolution
-from oracle.grid import fourier_diff_matrix
+from . import derivs as od
+from .evolve import Evolution
+from .grid import fourier_diff_matrix
+
 
 def bf16(x):
     """bfloat16 value of FP32 input (round to nearest even), returned as FP32."""

@@ -116,7 +116,7 @@ def gauge_perturbation(seed, r, theta, phi, amp=1e-6, r0=6.0, width=1.0):
 # Shell lists of the benchmark workloads: (N_r, N_theta, N_phi, r_min, r_max),
 # identical shells adjacent so that they run as one batch.  Shell k draws its
 # perturbation with seed base + k (gauge fields: base + 1000 + k).
-WORKLOAD_SEED = {"ks33": 2, "ks49": 2, "batch64": 4000, "large8": 5000}
+WORKLOAD_SEED = {"ks33": 2, "ks49": 3, "batch64": 4000, "large8": 5000}
 
 
 def workload_shells(name):

@@ -8,10 +8,17 @@ and the state after the listed step counts is stored at a fixed seeded sample
 of indices (the whole state is too large to keep), together with full-state
 norms of the state and of its change since t = 0.
 
-Usage: python tests/golden/make_oracle_evolutions.py CASE [CASE ...]
+With --mode fp32, bf16x3 or bf16 the angular derivative products of every
+right-hand side are carried out in that mode's rounding (oracle.rounding;
+everything else stays the oracle's FP64 code): the prediction of the state a
+reduced-precision run must reach, written to oracle_<case>_<mode>.npz.
+
+Usage: python tests/golden/make_oracle_evolutions.py [--mode MODE] [--steps N] CASE [CASE ...]
 Cases: shell17_100, shell33_100, shell49_100 (see CASES).  Each writes
-tests/golden/oracle_<case>.npz; the 49 x 48 x 96 case takes about an hour.
+tests/golden/oracle_<case>[_<mode>].npz; the 49 x 48 x 96 case takes about
+an hour per mode.  --steps N keeps only the stored step counts <= N.
 """
+import argparse
 import os
 import sys
 import time
@@ -24,6 +31,7 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 from oracle.grid import Shell, courant_dt            # noqa: E402
 from oracle import initial_data as oid              # noqa: E402
 from oracle.evolve import Evolution                 # noqa: E402
+from oracle.rounding import RoundedEvolution        # noqa: E402
 from paper_1104_3408_amd import inputs              # noqa: E402
 
 # name: (N_r, N_theta, r_min, r_max, perturbation seed, stored step counts)
@@ -48,17 +56,23 @@ def sample_indices(shape):
     return np.array(sorted(idx), dtype=np.int64)
 
 
-def run(name):
+def run(name, mode="fp64", max_steps=None):
     n_r, n_th, r0, r1, seed, saves = CASES[name]
+    if max_steps is not None:
+        saves = tuple(n for n in saves if n <= max_steps)
     sh = Shell(n_r, n_th, 2 * n_th, r0, r1)
     g10 = inputs.perturbed_kerr_schild(seed, sh.r, sh.theta, sh.phi)
     u0 = oid.first_order_data(g10, sh)
     H, dH = oid.static_gauge(u0, sh)
-    ev = Evolution(sh, 50, H, dH, "Yn", 4)
+    if mode == "fp64":
+        ev = Evolution(sh, 50, H, dH, "Yn", 4)
+    else:
+        ev = RoundedEvolution(sh, 50, H, dH, "Yn", 4, mode=mode)
     dt = courant_dt(sh)
     idx = sample_indices(u0.shape)
     out = {"idx": idx, "dt": np.float64(dt), "shape": np.array(u0.shape, dtype=np.int64),
-           "steps": np.array(saves, dtype=np.int64), "max_u0": np.float64(np.abs(u0).max())}
+           "steps": np.array(saves, dtype=np.int64), "max_u0": np.float64(np.abs(u0).max()),
+           "seed": np.int64(seed), "radii": np.array([r0, r1]), "mode": np.array(mode)}
     u = u0
     t0 = time.time()
     for n in range(1, max(saves) + 1):
@@ -70,10 +84,16 @@ def run(name):
             out["rms_u_%d" % n] = np.float64(np.sqrt(np.mean(u ** 2)))
             out["max_du_%d" % n] = np.float64(np.abs(ch).max())
             out["rms_du_%d" % n] = np.float64(np.sqrt(np.mean(ch ** 2)))
-        print("%s: step %d, %.0f s" % (name, n, time.time() - t0), flush=True)
-    np.savez(os.path.join(HERE, "oracle_%s.npz" % name), **out)
+        print("%s %s: step %d, %.0f s" % (name, mode, n, time.time() - t0), flush=True)
+    suffix = "" if mode == "fp64" else "_" + mode
+    np.savez(os.path.join(HERE, "oracle_%s%s.npz" % (name, suffix)), **out)
 
 
 if __name__ == "__main__":
-    for case in sys.argv[1:]:
-        run(case)
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--mode", default="fp64", choices=["fp64", "fp32", "bf16x3", "bf16"])
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("cases", nargs="+", choices=sorted(CASES))
+    a = ap.parse_args()
+    for case in a.cases:
+        run(case, a.mode, a.steps)

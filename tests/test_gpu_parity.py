@@ -13,12 +13,13 @@ torch = pytest.importorskip("torch")
 
 from paper_1104_3408_amd import shellspec as ss
 from paper_1104_3408_amd import inputs
-from oracle.grid import Shell
+from oracle.grid import Shell, courant_dt
 from oracle import derivs as od
 from oracle import tensor_filter as otf
 from oracle import initial_data as oid
 from oracle.evolve import Evolution
 from oracle import ghg
+from oracle.rounding import RoundedEvolution
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
@@ -340,45 +341,102 @@ def test_kernel_timing_classes():
     assert all(m > 0 for m in ms)
 
 
-@pytest.mark.parametrize("prec,unit", [(ss.SG_PREC_FP32, 2.0 ** -24), (ss.SG_PREC_BF16X3, 2.0 ** -16)])
-@pytest.mark.parametrize("n_r,n_th,steps,kind", [(13, 12, 5, "Yn"), (49, 48, 1, "Yn"), (13, 12, 5, "Y"),
-                                                 (33, 32, 2, "Yn")])
-def test_mixed_precision_error(n_r, n_th, steps, kind, prec, unit):
-    """SG_PREC_FP32: angular derivatives in FP32 and the filter split as
-    F(u) = F(u_ref) + F32(u - u_ref) (d_r, rhs and the RK state in FP64),
-    against the FP64 oracle.  Stated bound, relative to max|u|: one rounding
-    unit of the angular operator per step, amplified by the chain rule,
-    steps * dt * unit * ||D||_inf / (r_min sin theta_0); ||D||_inf is the
-    row-sum norm of the Fourier derivative on N_phi = 2 N_theta points (the phi
-    matrix and the double-cover theta matrix share it).  The split filter's
-    rounding is relative to |u - u_ref| and adds nothing visible.
-    SG_PREC_BF16X3: the same with the angular contractions on the matrix
-    cores from two-part bfloat16 operands (W_hi x_hi + W_hi x_lo + W_lo x_hi in
-    FP32); each product then carries at most 3 * 2^-18 of |W||x| (the dropped
-    W_lo x_lo and the two split residuals, each <= 2^-9 * 2^-9), so the unit
-    is 2^-16."""
-    g = ss.ShellGrid([(n_r, n_th, 2 * n_th, 1.8, 11.8)], precision=prec, filter=kind)
-    sh = Shell(n_r, n_th, 2 * n_th, 1.8, 11.8)
-    g10 = inputs.perturbed_kerr_schild(3, sh.r, sh.theta, sh.phi)
-    u = oid.first_order_data(g10, sh)
-    H, dH = oid.static_gauge(u, sh)
-    g.set_gauge(dev(H))
-    ut = dev(u)
-    g.rk_step(ut, steps)
-    ev = Evolution(sh, 50, H, dH, kind, 4)
-    ref = u
-    dt = g.info(0)[2]
-    for _ in range(steps):
-        ref = ev.rk4_step(ref, dt)
-    got = host(ut).reshape(u.shape)
-    err = rel(got, ref)
-    n = 2 * n_th
-    d_norm = np.sum(0.5 / np.abs(np.tan(np.pi * np.arange(1, n) / n)))
-    bound = steps * dt * unit * d_norm / (1.8 * np.sin(np.pi / (2 * n_th)))
-    print("precision %d %dx%dx%d after %d steps: max rel err %.3e (bound %.3e)" % (prec, n_r, n_th, n, steps, err,
-                                                                                   bound))
-    assert err < bound, (err, bound)
-    assert err > 1e-13       # really computed in reduced precision
+# Reduced precision is held to the error the oracle predicts for the mode
+# when its angular products are carried out in that mode's rounding
+# (oracle.rounding): within MIXED_FACTOR in max and in RMS.  On these cases
+# the GPU measured 0.7 to 2.1 times the prediction; the predictions of the
+# modes differ by factors of about 100 (FP32 to BF16x3) and 300 (BF16x3 to
+# plain bfloat16 operands), so a result computed in another precision falls
+# outside the band.
+MIXED_FACTOR = 3.0
+_MODEL_CACHE = {}
+
+
+def _mixed_case(n_r, n_th, steps, kind):
+    """Oracle initial state, its FP64 evolution and the rounding model's
+    states for fp32, bf16x3 and bf16 after `steps` filtered steps."""
+    key = (n_r, n_th, steps, kind)
+    if key not in _MODEL_CACHE:
+        sh = Shell(n_r, n_th, 2 * n_th, 1.8, 11.8)
+        g10 = inputs.perturbed_kerr_schild(3, sh.r, sh.theta, sh.phi)
+        u = oid.first_order_data(g10, sh)
+        H, dH = oid.static_gauge(u, sh)
+        dt = courant_dt(sh)
+        out = {}
+        for mode in ("fp64", "fp32", "bf16x3", "bf16"):
+            ev = (Evolution(sh, 50, H, dH, kind, 4) if mode == "fp64" else
+                  RoundedEvolution(sh, 50, H, dH, kind, 4, mode=mode))
+            x = u
+            for _ in range(steps):
+                x = ev.rk4_step(x, dt)
+            out[mode] = x
+        _MODEL_CACHE[key] = (sh, u, H, dt, out)
+    return _MODEL_CACHE[key]
+
+
+def _err(a, ref):
+    d = a - ref
+    return np.abs(d).max() / np.abs(ref).max(), np.sqrt(np.mean(d ** 2)) / np.sqrt(np.mean(ref ** 2))
+
+
+@pytest.mark.parametrize("n_r,n_th,steps,kind", [(13, 12, 5, "Yn"), (13, 12, 5, "Y"), (17, 16, 10, "Yn"),
+                                                 (77, 8, 3, "Yn"), (33, 32, 2, "Yn")])
+def test_mixed_precision_matches_rounding_model(n_r, n_th, steps, kind):
+    """SG_PREC_FP32 (angular derivatives in FP32; filter split as
+    F(u_ref) + F32(u - u_ref)) and SG_PREC_BF16X3 (angular contractions on
+    the matrix cores from two-part bfloat16 operands) after `steps` filtered
+    steps, against the FP64 oracle: max and RMS error within MIXED_FACTOR of
+    the oracle's prediction for the mode.  77 x 8 x 16 takes the separate
+    (forked) derivative launches of both modes (the radial operator needs 12
+    waves there)."""
+    sh, u, H, dt, model = _mixed_case(n_r, n_th, steps, kind)
+    ref = model["fp64"]
+    e_b3, e_16 = _err(model["bf16x3"], ref), _err(model["bf16"], ref)
+    e_32 = _err(model["fp32"], ref)
+    for i in range(2):          # the predictions of the modes are apart by more than the band
+        assert e_16[i] > MIXED_FACTOR ** 2 * e_b3[i] and e_b3[i] > MIXED_FACTOR ** 2 * e_32[i], (e_32, e_b3, e_16)
+    for prec, mode in ((ss.SG_PREC_FP32, "fp32"), (ss.SG_PREC_BF16X3, "bf16x3")):
+        g = ss.ShellGrid([(n_r, n_th, 2 * n_th, 1.8, 11.8)], precision=prec, filter=kind)
+        assert g.info(0)[2] == pytest.approx(dt, rel=1e-15)
+        g.set_gauge(dev(H))
+        ut = dev(u)
+        g.rk_step(ut, steps)
+        got = host(ut).reshape(u.shape)
+        e, p = _err(got, ref), _err(model[mode], ref)
+        print("%s %dx%dx%d %s after %d steps: max %.3e rms %.3e, predicted max %.3e rms %.3e" % (
+            mode, n_r, n_th, 2 * n_th, kind, steps, e[0], e[1], p[0], p[1]))
+        for i in range(2):
+            assert p[i] / MIXED_FACTOR <= e[i] <= MIXED_FACTOR * p[i], (mode, e, p)
+        g.close()
+
+
+@pytest.mark.parametrize("shape", [(13, 8, 16), (33, 32, 64), (17, 16, 32)])
+def test_bf16x3_fused_launch_matches_separate_launches(shape):
+    """SG_PREC_BF16X3: the one-launch form of a stage's derivatives
+    (k_derivs3_bf3, 8 waves per workgroup; the captured step) and the separate
+    launches of the timing mode (4 waves) run the same FP64 radial tile and
+    the same matrix-core blocks; only the summation order of the FP64 circle
+    means differs, which can move an FP32-rounded input by one unit.  After
+    three steps the two states agree to 2^-8 of their distance from the FP64
+    result, far below what a skipped or stale tile would leave (a whole
+    step's change)."""
+    n_r, n_th, n_ph = shape
+    states = {}
+    for prec, timing in ((ss.SG_PREC_FP64, False), (ss.SG_PREC_BF16X3, False), (ss.SG_PREC_BF16X3, True)):
+        g = ss.ShellGrid([(n_r, n_th, n_ph, 1.8, 11.8)], precision=prec)
+        r, th, ph = g.coords(0)
+        u = torch.zeros(g.state_size, dtype=torch.float64, device="cuda")
+        g.kerr_schild_data(dev(inputs.perturbed_kerr_schild(2, r, th, ph).ravel()), u)
+        g.enable_timing(timing)
+        g.rk_step(u, 3)
+        g.enable_timing(False)
+        states[(prec, timing)] = host(u)
+        g.close()
+    ref = states[(ss.SG_PREC_FP64, False)]
+    fused, sep = states[(ss.SG_PREC_BF16X3, False)], states[(ss.SG_PREC_BF16X3, True)]
+    dist = np.abs(fused - ref).max()
+    assert dist > 1e-10                                     # really BF16x3
+    assert np.abs(fused - sep).max() <= 2.0 ** -8 * dist, (np.abs(fused - sep).max(), dist)
 
 
 @pytest.mark.parametrize("n_v", [50, 58])

@@ -1,10 +1,10 @@
-"""Pins of the reduced-precision rounding model used by the mixed-precision
-parity tests (CPU only)."""
+"""Pins of the oracle's reduced-precision products (oracle.rounding), used by
+the mixed-precision parity tests (CPU only)."""
 import numpy as np
 import pytest
 import torch
 
-from rounding_model import bf16, split, product, RoundedEvolution
+from oracle.rounding import bf16, split, product, RoundedEvolution
 from oracle.grid import Shell, courant_dt, fourier_diff_matrix
 from oracle import initial_data as oid
 from paper_1104_3408_amd import inputs
