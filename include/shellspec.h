@@ -154,6 +154,22 @@ sg_status swsh_filter(sg_grid* g, double* u, sg_stream_t stream);
  * workspace, so calls on one grid must not overlap.  SG_EINVAL on NULL. */
 sg_status ghg_constraints(sg_grid* g, const double* u, double* norms, sg_stream_t stream);
 
+/* The constraint monitor of ghg_constraints for callers that cannot allocate
+ * device memory (code captured into a graph, serving loops, harnesses that
+ * forbid allocation): the call makes no allocation and uses no workspace of
+ * the grid.  du_cart: caller-owned device array with the Cartesian
+ * derivatives of the state as spec_derivs writes them in SG_CART mode (per
+ * shell 3 blocks of the shell's state size; only the ten g_ab of each block
+ * are read).  norms as for ghg_constraints.  The workgroup partials live in
+ * a fixed 128 KB device array of the library (one per device, held until the
+ * process ends), which limits a shell to 4096 x 256 grid points (every shell
+ * shell_grid_create accepts fits; larger: SG_ESHAPE).  Calls that overlap on
+ * one device (several streams or host threads) share that array and race;
+ * calls in one stream order are safe.  Stream-ordered; SG_EINVAL on NULL,
+ * SG_EHIP on a launch error. */
+sg_status ghg_constraints_static(const sg_grid* g, const double* u, const double* du_cart, double* norms,
+                                 sg_stream_t stream);
+
 /* Right-hand side d_t u of the first-order GHG system (App. A.1 eqs. gdot,
  * Phidot, Pidot with gamma_0 = gamma_2 = 1, gamma_1 = -1), with the
  * freezing-incoming boundary operator (App. A.3) applied on the outermost

@@ -372,6 +372,8 @@ std::vector<Run> make_runs(const sg_grid* g, const double* dts) {
 
 }  // namespace
 
+sg_status sg::set_error(sg_status st, const std::string& msg) { return fail(st, msg); }
+
 KShell ShellHost::view(int n_v) const {
     KShell k;
     k.n_r = d.n_r;
@@ -689,7 +691,7 @@ sg_status ghg_constraints(sg_grid* g, const double* u, double* norms, sg_stream_
         const KShell v = S.view(g->opt.n_fields);
         // Cartesian derivatives of the ten g_ab of this shell into the workspace
         HIP_TRY(derivs_shell(g, s, u + S.off, g->dbuf, 10, true, st));
-        HIP_TRY(launch_constraints(v, u + S.off, g->dbuf, g->cpart, norms + 4 * s, st));
+        HIP_TRY(launch_constraints(v, u + S.off, g->dbuf, 10LL * (long long)S.npts, g->cpart, norms + 4 * s, st));
     }
     return SG_OK;
 }

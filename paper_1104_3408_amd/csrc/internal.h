@@ -177,6 +177,9 @@ struct sg_grid {
 };
 
 namespace sg {
+// Record msg as the calling thread's last error (sg_last_error) and return st.
+sg_status set_error(sg_status st, const std::string& msg);
+
 // Launchers (stream-ordered; return a HIP error code).
 hipError_t launch_dr(const KShell& s, const double* in, double* out, int n_fields, hipStream_t st);
 hipError_t launch_dtheta(const KShell& s, const double* in, double* out, int n_fields, hipStream_t st);
@@ -230,9 +233,10 @@ hipError_t launch_ftheta(const KShell& s, int count, const double* spec, double*
 hipError_t launch_initial(const KShell& s, const double* g10, const double* dg, double* u,
                           double* H, hipStream_t st);
 hipError_t launch_finite_check(const double* u, size_t n, int* flag, hipStream_t st);
+// dg: Cartesian derivatives of the ten g_ab, block x at dg + x * dblk;
 // part: ceil(npts/256) * 4 doubles of workspace; norms: 4 doubles.
-hipError_t launch_constraints(const KShell& s, const double* u, const double* dg, double* part, double* norms,
-                              hipStream_t st);
+hipError_t launch_constraints(const KShell& s, const double* u, const double* dg, long long dblk, double* part,
+                              double* norms, hipStream_t st);
 // norms (4 doubles) from the constraint partials of one shell.
 hipError_t launch_constraint_norms(const KShell& s, const double* part, double* norms, hipStream_t st);
 }  // namespace sg

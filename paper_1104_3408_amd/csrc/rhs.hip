@@ -514,10 +514,12 @@ __global__ __launch_bounds__(256) void k_initial(KShell s, const double* __restr
 
 // Constraint fields of App. A.1 at every point of a shell, reduced per
 // workgroup: C_a = H_a + Gamma_a and C_iab = d_i g_ab - Phi_iab with d_i g_ab
-// the Cartesian spectral derivative dg[i][pair][point].  part[blk][4] =
-// (max |C_a|, sum C_a^2, max |C_iab|, sum C_iab^2) over the workgroup's points.
+// the Cartesian spectral derivative dg[i * dblk + pair * npts + point] (dblk:
+// stride between the x, y, z blocks).  part[blk][4] = (max |C_a|, sum C_a^2,
+// max |C_iab|, sum C_iab^2) over the workgroup's points.
 __global__ __launch_bounds__(256) void k_constraints(KShell s, const double* __restrict__ u,
-                                                     const double* __restrict__ dg, double* __restrict__ part) {
+                                                     const double* __restrict__ dg, long long dblk,
+                                                     double* __restrict__ part) {
     __shared__ double red[4][256];
     const long long np = s.npts;
     const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -528,7 +530,7 @@ __global__ __launch_bounds__(256) void k_constraints(KShell s, const double* __r
         for (int x = 0; x < 3; ++x)
 #pragma unroll
             for (int q = 0; q < 10; ++q) {
-                const double ci = dg[(x * 10 + q) * np + p] - u[(20 + 10 * x + q) * np + p];
+                const double ci = dg[x * dblk + q * np + p] - u[(20 + 10 * x + q) * np + p];
                 mxi = fmax(mxi, fabs(ci));
                 ssi += ci * ci;
             }
@@ -612,10 +614,10 @@ hipError_t launch_initial(const KShell& s, const double* g10, const double* dg, 
     return hipGetLastError();
 }
 
-hipError_t launch_constraints(const KShell& s, const double* u, const double* dg, double* part, double* norms,
-                              hipStream_t st) {
+hipError_t launch_constraints(const KShell& s, const double* u, const double* dg, long long dblk, double* part,
+                              double* norms, hipStream_t st) {
     const unsigned blocks = (unsigned)((s.npts + 255) / 256);
-    hipLaunchKernelGGL(k_constraints, dim3(blocks), dim3(256), 0, st, s, u, dg, part);
+    hipLaunchKernelGGL(k_constraints, dim3(blocks), dim3(256), 0, st, s, u, dg, dblk, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_constraint_norms(s, part, norms, st);

@@ -57,6 +57,7 @@ _SIGS = {
     "swsh_filter": (ctypes.c_int, [_P, _P, _P]),
     "ghg_rhs": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "ghg_constraints": (ctypes.c_int, [_P, _P, _P, _P]),
+    "ghg_constraints_static": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "rk_step": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P]),
     "sg_kerr_schild_data": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "sg_enable_timing": (ctypes.c_int, [_P, ctypes.c_int]),
@@ -197,6 +198,13 @@ class ShellGrid:
         (max |C_a|, rms C_a, max |C_iab|, rms C_iab)."""
         _check(lib().ghg_constraints(self.h, _ptr(u, self.state_size), _ptr(norms, 4 * len(self.shells)),
                                      _stream(stream)))
+
+    def ghg_constraints_static(self, u, du_cart, norms, stream=None):
+        """ghg_constraints from caller-given Cartesian derivatives (spec_derivs
+        SG_CART layout), with no allocation in the library."""
+        n = self.state_size
+        _check(lib().ghg_constraints_static(self.h, _ptr(u, n), _ptr(du_cart, 3 * n),
+                                            _ptr(norms, 4 * len(self.shells)), _stream(stream)))
 
     def rk_step(self, u, n_steps=1, dt=None, stream=None):
         arr = None
