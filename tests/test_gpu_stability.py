@@ -1,9 +1,9 @@
 """Long filtered evolutions on the GPU against the stability findings of the
 paper's single black hole runs (r in [1.8, 11.8], Courant factor 4):
 
-* Sec. 4.2 (Fig. r10_nf): with the tensor filter, n_f = 0, 1, 2 fail within
+* Sec. 4.1 (Fig. r10_nf): with the tensor filter, n_f = 0, 1, 2 fail within
   t = 110 while n_f >= 3 stay bounded;
-* Sec. 4.2 (Fig. r10_f0, r10_f1): the scalar Y filter (n_f = 4) fails after a
+* Sec. 4.1 (Fig. r10_f0, r10_f1): the scalar Y filter (n_f = 4) fails after a
   few thousand time units while the tensor filter keeps running.
 
 The monitored quantity is the paper's: max |d_t g_tt| over the shell, from
