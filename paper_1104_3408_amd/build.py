@@ -17,7 +17,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libshellspec.so")
 
-SOURCES = ["api.hip", "derivs.hip", "rhs.hip", "filter.hip", "bf16x3.hip", "noalloc.hip", "host_math.cpp"]
+SOURCES = ["api.hip", "derivs.hip", "rhs.hip", "filter.hip", "bf16x3.hip", "noalloc.hip", "host_math.cpp",
+           "tuning.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

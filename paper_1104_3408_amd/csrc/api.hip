@@ -110,9 +110,9 @@ sg_status check_opts(const sg_shell_desc* shells, int n_shells, const sg_options
 
 void free_shell(ShellHost& s) {
     if (!s.owns_ops) return;   // operators shared with an earlier identical shell
-    for (double* p : {s.Drb, s.Hsb, s.Hab, s.dph.Wb, s.ana.Wb, s.syn.Wb, s.rk, s.sth, s.cth, s.sph, s.cph, s.Fb})
+    for (double* p : {s.Drb, s.Hsb, s.dph.Wb, s.ana.Wb, s.syn.Wb, s.rk, s.sth, s.cth, s.sph, s.cph, s.Fb})
         if (p) (void)hipFree(p);
-    for (float* p : {s.Hsb_f, s.Hab_f, s.dph.Wb_f, s.ana.Wb_f, s.syn.Wb_f, s.Fb_f})
+    for (float* p : {s.Hsb_f, s.dph.Wb_f, s.ana.Wb_f, s.syn.Wb_f, s.Fb_f})
         if (p) (void)hipFree(p);
     for (uint16_t* p : {s.bf_dph.hi, s.bf_dph.lo, s.bf_hs.hi, s.bf_hs.lo, s.bf_ha.hi, s.bf_ha.lo})
         if (p) (void)hipFree(p);
@@ -297,7 +297,7 @@ hipError_t filter_run(sg_grid* g, const Run& R, double* u, hipStream_t st) {
     }
     {
         TimeScope ts(g, SG_K_FTHETA, st);
-        const FiltPlan fp{S.Fb, S.Fb_f, g->d_groups, g->d_fsets, (int)g->fsets.size(), g->max_groups, S.F_R};
+        const FiltPlan fp{S.Fb, S.Fb_f, g->d_groups, g->d_fsets, (int)g->fsets.size(), g->max_groups, S.F_R, S.F_nw};
         if ((e = launch_ftheta(v, R.count, g->spec, g->spec2, fp, g->n_cols, S.m_keep, st)) != hipSuccess)
             return e;
     }
@@ -339,7 +339,7 @@ hipError_t filter_run_split(sg_grid* g, const Run& R, double* u, hipStream_t st)
     }
     {
         TimeScope ts(g, SG_K_FTHETA, st);
-        const FiltPlan fp{S.Fb, S.Fb_f, g->d_groups, g->d_fsets, (int)g->fsets.size(), g->max_groups, S.F_R};
+        const FiltPlan fp{S.Fb, S.Fb_f, g->d_groups, g->d_fsets, (int)g->fsets.size(), g->max_groups, S.F_R, S.F_nw};
         if ((e = launch_ftheta_f32(v, R.count, spec, spec2, fp, g->n_cols, S.m_keep, st)) != hipSuccess) return e;
     }
     {
@@ -383,13 +383,11 @@ KShell ShellHost::view(int n_v) const {
     k.npts = (long long)npts;
     k.Drb = Drb;
     k.Hsb = Hsb;
-    k.Hab = Hab;
     k.Dr_R = Dr_R;
     k.Hth_R = Hth_R;
     k.Dr_nw = Dr_nw;
     k.Hth_nw = Hth_nw;
     k.Hsb_f = Hsb_f;
-    k.Hab_f = Hab_f;
     k.rk = rk;
     k.sth = sth;
     k.cth = cth;
@@ -425,6 +423,7 @@ sg_status shell_grid_create(const sg_shell_desc* shells, int n_shells, const sg_
     for (int s = 0; s < n_shells; ++s) {
         ShellHost S;
         S.d = shells[s];
+        S.tune = lookup_tuning(S.d.n_r, S.d.n_theta, opt->n_fields, opt->precision, nullptr);
         const int nr = S.d.n_r, nt = S.d.n_theta, np_ = S.d.n_phi, L = nt - 1;
         S.npts = size_t(nr) * nt * np_;
         S.count = S.npts * opt->n_fields;
@@ -450,12 +449,12 @@ sg_status shell_grid_create(const sg_shell_desc* shells, int n_shells, const sg_
         }
         if (twin >= 0) {
             const ShellHost& T = g->sh[twin];
-            S.Drb = T.Drb; S.Hsb = T.Hsb; S.Hab = T.Hab; S.Hsb_f = T.Hsb_f; S.Hab_f = T.Hab_f;
+            S.Drb = T.Drb; S.Hsb = T.Hsb; S.Hsb_f = T.Hsb_f;
             S.Dr_R = T.Dr_R; S.Hth_R = T.Hth_R; S.Dr_nw = T.Dr_nw; S.Hth_nw = T.Hth_nw;
             S.dph = T.dph; S.ana = T.ana; S.syn = T.syn;
             S.bf_dph = T.bf_dph; S.bf_hs = T.bf_hs; S.bf_ha = T.bf_ha;
             S.rk = T.rk; S.sth = T.sth; S.cth = T.cth; S.sph = T.sph; S.cph = T.cph;
-            S.Fb = T.Fb; S.Fb_f = T.Fb_f; S.F_R = T.F_R;
+            S.Fb = T.Fb; S.Fb_f = T.Fb_f; S.F_R = T.F_R; S.F_nw = T.F_nw;
             S.owns_ops = false;
             g->sh.push_back(S);
             continue;
@@ -466,18 +465,17 @@ sg_status shell_grid_create(const sg_shell_desc* shells, int n_shells, const sg_
         for (int i = 0; i < nt; ++i) { sth[i] = std::sin(H.th_host[i]); cth[i] = std::cos(H.th_host[i]); }
         for (int j = 0; j < np_; ++j) { sph[j] = std::sin(H.ph_host[j]); cph[j] = std::cos(H.ph_host[j]); }
         const std::vector<double> fd = fourier_column(np_);
-        std::vector<double> ana, syn;
-        fourier_real_matrices(np_, H.m_keep, ana, syn);
-        // theta filters F^{|n|}_m, rows blocked over the 4 waves of k_ftheta
-        H.F_R = (nt + kFiltWaves - 1) / kFiltWaves;
-        const size_t per_mat = size_t(kFiltWaves) * nt * H.F_R;
+        // theta filters F^{|n|}_m, rows blocked over the waves of k_ftheta
+        H.F_nw = H.tune.filt_waves;
+        H.F_R = (nt + H.F_nw - 1) / H.F_nw;
+        const size_t per_mat = size_t(H.F_nw) * nt * H.F_R;
         std::vector<double> fm(size_t(g->n_sets) * (H.m_keep + 1) * per_mat, 0.0);
         for (int k = 0; k < g->n_sets; ++k) {
             const int n = set_spin(g, k), nf = set_nf(g, k);
             for (int m = 0; m <= H.m_keep; ++m) {
                 const std::vector<double> F = filter_matrix(n, m, nt, nf);
                 double* Fb = fm.data() + (size_t(k) * (H.m_keep + 1) + m) * per_mat;
-                for (int w = 0; w < kFiltWaves; ++w)
+                for (int w = 0; w < H.F_nw; ++w)
                     for (int ip = 0; ip < nt; ++ip)
                         for (int r = 0; r < H.F_R; ++r) {
                             const int i = w * H.F_R + r;
@@ -493,40 +491,99 @@ sg_status shell_grid_create(const sg_shell_desc* shells, int n_shells, const sg_
                 Ha[size_t(a) * nt + b] = hl - hr;
             }
         int passes = 0, passes_th = 0;
-        if (blocked_shape(nr, kDrRows, H.Dr_R, passes) != 0 || blocked_shape(nt, kThRows, H.Hth_R, passes_th) != 0)
+        const int hh = (nt + 1) / 2;   // theta rows of the equator-parity form
+        if (blocked_shape(nr, H.tune.dr_rows, H.Dr_R, passes) != 0 ||
+            blocked_shape(hh, H.tune.th_rows, H.Hth_R, passes_th) != 0)
             return cleanup(SG_ESHAPE, "radial or theta operator too large for one workgroup");
         H.Dr_nw = 4 * passes;
         H.Hth_nw = 4 * passes_th;
         std::vector<double> Drb = block_operator(cheb_matrix(nr, H.d.r_min, H.d.r_max), nr, nr, H.Dr_R, passes);
-        std::vector<double> Hsb = block_operator(Hs, nt, nt, H.Hth_R, passes_th),
-                            Hab = block_operator(Ha, nt, nt, H.Hth_R, passes_th);
+        // equator-parity form of Hs and Ha (dtheta_tile): for rows i < hh and
+        // inputs i' < hh, Q = (M_ii' + M_i,N-1-i') / 2 and P = (M_ii' - M_i,N-1-i') / 2
+        // (the middle input of an odd N_theta: Q = M_ii', P = 0), blocked
+        // [wave][i'][Qs (R), Ps (R), Qa (R), Pa (R)]
+        std::vector<double> Hsb(size_t(H.Hth_nw) * hh * 4 * H.Hth_R, 0.0);
+        for (int w = 0; w < H.Hth_nw; ++w)
+            for (int ip = 0; ip < hh; ++ip)
+                for (int r = 0; r < H.Hth_R; ++r) {
+                    const int i = w * H.Hth_R + r, im = nt - 1 - ip;
+                    if (i >= hh) continue;
+                    double* blk = Hsb.data() + (size_t(w) * hh + ip) * 4 * H.Hth_R;
+                    const double* M2[2] = {Hs.data() + size_t(i) * nt, Ha.data() + size_t(i) * nt};
+                    for (int op = 0; op < 2; ++op) {
+                        const double q = im == ip ? M2[op][ip] : 0.5 * (M2[op][ip] + M2[op][im]);
+                        const double pp = im == ip ? 0.0 : 0.5 * (M2[op][ip] - M2[op][im]);
+                        blk[(2 * op) * H.Hth_R + r] = q;
+                        blk[(2 * op + 1) * H.Hth_R + r] = pp;
+                    }
+                }
         auto to_f = [](const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); };
+        // d_phi in the parity form measured faster in FP32, the circulant
+        // window in FP64 (one per shell size: spec_derivs runs FP64 in every mode)
+        const bool dph_par = H.tune.dph_par >= 0 ? H.tune.dph_par == 1 : opt->precision == SG_PREC_FP32;
         // the Fourier derivative along phi is circulant: upload the doubled
-        // column vector, padded for the rows past n of the last wave
-        auto make_circ = [&](AxisOp& op, const std::vector<double>& col, int n) {
+        // column vector, padded for the rows past n of the last wave (the
+        // waves read their rows as a sliding window of it, which stays in the
+        // scalar cache)
+        auto make_circ = [&](AxisOp& op, const std::vector<double>& col, int n, int rows) {
             op.n_in = n;
             op.n_out = n;
             op.circ = 1;
-            if (blocked_shape(n, kAxisRows, op.R, op.passes) != 0) return hipErrorInvalidValue;
+            if (blocked_shape(n, rows, op.R, op.passes) != 0) return hipErrorInvalidValue;
             std::vector<double> dv(size_t(2 * n + 4 * op.R * op.passes), 0.0);
             for (int t = 0; t < 2 * n; ++t) dv[t] = col[((t - n) % n + n) % n];
             hipError_t e = upload(&op.Wb, dv);
             if (e != hipSuccess) return e;
             return upload(&op.Wb_f, to_f(dv));
         };
-        auto make_axis = [&](AxisOp& op, const std::vector<double>& W, int n_out, int n_in) {
-            op.n_in = n_in;
-            op.n_out = n_out;
-            if (blocked_shape(n_out, kAxisRows, op.R, op.passes) != 0) return hipErrorInvalidValue;
-            std::vector<double> Wb = block_operator(W, n_out, n_in, op.R, op.passes);
+        // phi contractions in the parity form of axis_par_tile: real Fourier
+        // analysis (kind 1), synthesis (kind 2) and the Fourier derivative
+        // (kind 3, FD[q][c] = fd[(q - c) mod N]); rows m (analysis) or
+        // j, q <= N/2, blocked [wave][input][C (R), S (R)]; Fourier angles
+        // from the integer j m mod N
+        auto make_axis_par = [&](AxisOp& op, int kind, int rows_target) {
+            const int n = np_, half = n / 2, mk = H.m_keep;
+            op.par = kind;
+            op.m_keep = kind == 3 ? 0 : mk;
+            op.n_in = kind == 2 ? 2 * mk + 1 : n;
+            op.n_out = kind == 1 ? 2 * mk + 1 : n;
+            const int rows = kind == 1 ? mk + 1 : half + 1, n_loop = kind == 2 ? mk + 1 : half + 1;
+            if (blocked_shape(rows, rows_target, op.R, op.passes) != 0) return hipErrorInvalidValue;
+            const int nw = 4 * op.passes, R = op.R;
+            auto v = [&](int d) { return fd[((d % n) + n) % n]; };
+            std::vector<double> Wb(size_t(nw) * n_loop * 2 * R, 0.0);
+            for (int w = 0; w < nw; ++w)
+                for (int jj = 0; jj < n_loop; ++jj)
+                    for (int r = 0; r < R; ++r) {
+                        const int q = w * R + r;
+                        if (q >= rows) continue;
+                        double c, sn;
+                        if (kind == 3) {   // e_jj and o_jj weights of row q
+                            const bool edge = jj == 0 || jj == half;
+                            c = edge ? v(q - jj) : 0.5 * (v(q - jj) + v(q + jj));
+                            sn = edge ? 0.0 : 0.5 * (v(q - jj) - v(q + jj));
+                        } else {
+                            const int j = kind == 1 ? jj : q, m = kind == 1 ? q : jj;
+                            const double ang = 2.0 * M_PI * (double)((long long)j * m % n) / n;
+                            c = std::cos(ang);
+                            sn = (m == 0 || j == 0 || j == half) ? 0.0 : std::sin(ang);
+                            if (kind == 1) {   // a_0 = (1/N) sum f, a_m, b_m = (2/N) sum (cos, sin) f
+                                c *= (m == 0 ? 1.0 : 2.0) / n;
+                                sn *= 2.0 / n;
+                            }
+                        }
+                        double* blk = Wb.data() + (size_t(w) * n_loop + jj) * 2 * R;
+                        blk[r] = c;
+                        blk[R + r] = sn;
+                    }
             hipError_t e = upload(&op.Wb, Wb);
             if (e != hipSuccess) return e;
             return upload(&op.Wb_f, to_f(Wb));
         };
         if (upload(&H.Drb, Drb) != hipSuccess || upload(&H.Hsb, Hsb) != hipSuccess ||
-            upload(&H.Hab, Hab) != hipSuccess || upload(&H.Hsb_f, to_f(Hsb)) != hipSuccess ||
-            upload(&H.Hab_f, to_f(Hab)) != hipSuccess || make_circ(H.dph, fd, np_) != hipSuccess ||
-            make_axis(H.ana, ana, H.K, np_) != hipSuccess || make_axis(H.syn, syn, np_, H.K) != hipSuccess ||
+            upload(&H.Hsb_f, to_f(Hsb)) != hipSuccess || (dph_par ? make_axis_par(H.dph, 3, H.tune.dph_rows) : make_circ(H.dph, fd, np_, H.tune.dph_rows)) != hipSuccess ||
+            make_axis_par(H.ana, 1, H.tune.ana_rows) != hipSuccess ||
+            make_axis_par(H.syn, 2, H.tune.syn_rows) != hipSuccess ||
             upload(&H.rk, H.r_host) != hipSuccess || upload(&H.sth, sth) != hipSuccess ||
             upload(&H.cth, cth) != hipSuccess || upload(&H.sph, sph) != hipSuccess ||
             upload(&H.cph, cph) != hipSuccess || upload(&H.Fb, fm) != hipSuccess ||

@@ -62,7 +62,7 @@ constexpr int kThMaxPerThread = 64 / kMinWaves;   // N_theta <= 64 rows over at 
 
 template <int R, typename T, typename O>
 __device__ __forceinline__ void dtheta_tile(long long tile, const double* __restrict__ in, O* __restrict__ out,
-                                            const T* __restrict__ Hsb, const T* __restrict__ Hab, int n_r, int n_th,
+                                            const T* __restrict__ Hsb, int n_r, int n_th,
                                             int n_ph, long long n_cols, double* __restrict__ smd) {
     // smd: S [n_th][64], A [n_th][64] in T, then partial sums [nw][64] in FP64
     T* sm = reinterpret_cast<T*>(smd);
@@ -123,20 +123,41 @@ __device__ __forceinline__ void dtheta_tile(long long tile, const double* __rest
         }
     }
     __syncthreads();
-    const T* Sw = Hsb + (long long)w * n_th * R;
-    const T* Aw = Hab + (long long)w * n_th * R;
-    T aS[R], aA[R];
+    // equator pairs (i, N_theta - 1 - i) -> (x + x', x - x') in place, for S and A
+    const int hh = (n_th + 1) / 2;   // rows i < hh; the middle row of an odd N_theta stays
+    for (int ip = w; ip < n_th / 2; ip += nw) {
+        const int im = n_th - 1 - ip;
+        const T s0 = sS[ip * 64 + lane], s1 = sS[im * 64 + lane];
+        const T a0 = sA[ip * 64 + lane], a1 = sA[im * 64 + lane];
+        sS[ip * 64 + lane] = s0 + s1;
+        sS[im * 64 + lane] = s0 - s1;
+        sA[ip * 64 + lane] = a0 + a1;
+        sA[im * 64 + lane] = a0 - a1;
+    }
+    __syncthreads();
+    // Hs and Ha are both anti-persymmetric (M[N-1-i][N-1-i'] = -M[i][i']: the
+    // double-cover circle is symmetric about the equator and the derivative is
+    // odd under the reflection), so with x+ = x_i' + x_{N-1-i'}, x- = x_i' - x_{N-1-i'}
+    // (i' < N/2; the middle row of an odd N enters x+ alone),
+    //   (M x)_i = Q x+ + P x-,  (M x)_{N-1-i} = P x- - Q x+,  i < N/2,
+    // Q_ii' = (M_ii' + M_i,N-1-i') / 2, P_ii' = (M_ii' - M_i,N-1-i') / 2: half the
+    // products of M.  Operator blocked as [w][i'][Qs (R), Ps (R), Qa (R), Pa (R)].
+    const T* Ww = Hsb + (long long)w * hh * 4 * R;
+    T qs[R], ps[R], qa[R], pa[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) aS[r] = aA[r] = (T)0;
-    #pragma unroll 4   // operator loads run ahead of the FMAs (measured against 1, 2, default)
-    for (int ip = 0; ip < n_th; ++ip) {
-        const T sv = sS[ip * 64 + lane], av = sA[ip * 64 + lane];
-        const T* hs = Sw + ip * R;
-        const T* ha = Aw + ip * R;
+    for (int r = 0; r < R; ++r) qs[r] = ps[r] = qa[r] = pa[r] = (T)0;
+    #pragma unroll 2
+    for (int ip = 0; ip < hh; ++ip) {
+        const int im = n_th - 1 - ip;   // = ip for the middle row (its P weights are 0)
+        const T sp = sS[ip * 64 + lane], sm_ = sS[im * 64 + lane];
+        const T ap = sA[ip * 64 + lane], am = sA[im * 64 + lane];
+        const T* wr = Ww + ip * 4 * R;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            aS[r] = fma(hs[r], sv, aS[r]);
-            aA[r] = fma(ha[r], av, aA[r]);
+            qs[r] = fma(wr[r], sp, qs[r]);
+            ps[r] = fma(wr[R + r], sm_, ps[r]);
+            qa[r] = fma(wr[2 * R + r], ap, qa[r]);
+            pa[r] = fma(wr[3 * R + r], am, pa[r]);
         }
     }
     if (cok) {
@@ -144,9 +165,16 @@ __device__ __forceinline__ void dtheta_tile(long long tile, const double* __rest
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int i = w * R + r;
-            if (i < n_th) {
-                o[(long long)i * n_r] = (O)((T)0.5 * (aS[r] + aA[r]));
-                o[half * plane + (long long)i * n_r] = (O)((T)0.5 * (aS[r] - aA[r]));
+            if (i < hh) {
+                const T hs = qs[r] + ps[r], ha = qa[r] + pa[r];
+                o[(long long)i * n_r] = (O)((T)0.5 * (hs + ha));
+                o[half * plane + (long long)i * n_r] = (O)((T)0.5 * (hs - ha));
+                const int im = n_th - 1 - i;
+                if (im != i) {
+                    const T hs2 = ps[r] - qs[r], ha2 = pa[r] - qa[r];
+                    o[(long long)im * n_r] = (O)((T)0.5 * (hs2 + ha2));
+                    o[half * plane + (long long)im * n_r] = (O)((T)0.5 * (hs2 - ha2));
+                }
             }
         }
     }
@@ -154,10 +182,10 @@ __device__ __forceinline__ void dtheta_tile(long long tile, const double* __rest
 
 template <int R, typename T, typename O>
 __global__ __launch_bounds__(1024) void k_dtheta(const double* __restrict__ in, O* __restrict__ out,
-                                                const T* __restrict__ Hsb, const T* __restrict__ Hab,
+                                                const T* __restrict__ Hsb,
                                                 int n_r, int n_th, int n_ph, long long n_cols) {
     extern __shared__ double smd[];
-    dtheta_tile<R, T, O>(blockIdx.x, in, out, Hsb, Hab, n_r, n_th, n_ph, n_cols, smd);
+    dtheta_tile<R, T, O>(blockIdx.x, in, out, Hsb, n_r, n_th, n_ph, n_cols, smd);
 }
 
 // out[f][q][c] = sum_r W[q][r] (in[f][r][c] - m_c),  m_c = mean of column c
@@ -241,6 +269,120 @@ __global__ __launch_bounds__(1024) void k_axis(const I* __restrict__ in, O* __re
     axis_tile<R, I, T, O, CIRC>(blockIdx.x, blockIdx.y, in, out, Wb, n_in, n_out, ncol, center, smd);
 }
 
+// Contractions along phi in the parity form (MODE: kParAna, kParSyn,
+// kParDphi).  About phi = 0 cos is even and sin odd, and the Fourier
+// derivative matrix FD[q][c] = v[(q - c) mod N] has v odd, so with
+// e_j = f_j + f_{N-j}, o_j = f_j - f_{N-j} (0 < j < N/2; e_0 = f_0,
+// e_{N/2} = f_{N/2}):
+//   analysis (Sec. 3.1 eq. Fanalysis): a_m = sum_{0 <= j <= N/2} C[m][j] e_j,
+//     b_m = sum_{0 < j < N/2} S[m][j] o_j;
+//   synthesis (eq. Fsynthesis): f_j = A_j + B_j, f_{N-j} = A_j - B_j with
+//     A_j = sum_m C[j][m] a_m, B_j = sum_{m >= 1} S[j][m] b_m, 0 <= j <= N/2;
+//   d_phi (Sec. 2.3, eq. D3; the circle mean removed first, the rows of FD
+//     annihilate constants): y_q = A_q + B_q, y_{N-q} = B_q - A_q with
+//     A_q = sum_{0 <= j <= N/2} C[q][j] e_j, B_q = sum_{0 < j < N/2} S[q][j] o_j,
+//     C[q][j] = (v[q - j] + v[q + j]) / 2 (v[q], v[q - N/2] at j = 0, N/2),
+//     S[q][j] = (v[q - j] - v[q + j]) / 2:
+// half the products of the full matrices (and half the operator, which the
+// waves read through the scalar cache).  Spectral rows are q = 0 (a_0),
+// 2m - 1 (a_m), 2m (b_m).  Wave w forms the row pair (a_m, b_m), (A_j, B_j)
+// resp. (A_q, B_q) for m, j resp. q = w R + r; the operator is wave-blocked
+// as Wb[w][input][C (R values), S (R values)], zero past the last row and
+// where S vanishes.  The analysis and d_phi rewrite the staged rows j, N - j
+// into e_j, o_j in place.
+constexpr int kParAna = 0, kParSyn = 1, kParDphi = 2;
+
+template <int R, typename I, typename T, typename O, int MODE>
+__device__ __forceinline__ void axis_par_tile(long long tile, int f, const I* __restrict__ in, O* __restrict__ out,
+                                              const T* __restrict__ Wb, int n_ph, int m_keep, long long ncol,
+                                              double* __restrict__ smd) {
+    constexpr bool SYN = MODE == kParSyn;
+    const int nw = blockDim.x >> 6;
+    T* sm = reinterpret_cast<T*>(smd);   // [n_in][64], then (d_phi) partial sums [nw][64] in FP64
+    double* spart = reinterpret_cast<double*>(sm + n_ph * 64);
+    const int half = n_ph / 2;
+    const int n_in = SYN ? 2 * m_keep + 1 : n_ph;
+    const int n_out = MODE == kParAna ? 2 * m_keep + 1 : n_ph;
+    const long long c0 = tile * 64;
+    const int nc = (int)min((long long)64, ncol - c0);
+    const I* src = in + (long long)f * n_in * ncol + c0;
+    const int lane = threadIdx.x & 63;
+    const int w = wave_id();
+    const int lc = lane < nc ? lane : 0;   // an in-bounds column for every lane
+    double v[kAxisMaxIn / kMinWaves];
+#pragma unroll
+    for (int t = 0; t < kAxisMaxIn / kMinWaves; ++t) {
+        const int r = w + nw * t;
+        v[t] = (r < n_in) ? (double)src[(long long)r * ncol + lc] : 0.0;
+    }
+    double mc = 0.0;
+    if (MODE == kParDphi) {   // column mean over phi, in FP64 from the waves' partial sums
+        double part = 0.0;
+#pragma unroll
+        for (int t = 0; t < kAxisMaxIn / kMinWaves; ++t) part += v[t];
+        spart[w * 64 + lane] = part;
+        __syncthreads();
+        for (int q = 0; q < nw; ++q) mc += spart[q * 64 + lane];
+        mc /= n_in;
+    }
+#pragma unroll
+    for (int t = 0; t < kAxisMaxIn / kMinWaves; ++t) {
+        const int r = w + nw * t;
+        if (r < n_in) sm[r * 64 + lane] = (T)(v[t] - mc);
+    }
+    __syncthreads();
+    if (!SYN) {
+        for (int j = 1 + w; j < half; j += nw) {
+            const T a = sm[j * 64 + lane], b = sm[(n_ph - j) * 64 + lane];
+            sm[j * 64 + lane] = a + b;
+            sm[(n_ph - j) * 64 + lane] = a - b;
+        }
+        __syncthreads();
+    }
+    const int n_loop = SYN ? m_keep + 1 : half + 1;
+    const T* Ww = Wb + (long long)w * n_loop * 2 * R;
+    T ac[R], as[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) ac[r] = as[r] = (T)0;
+    #pragma unroll 4
+    for (int jj = 0; jj < n_loop; ++jj) {
+        // analysis, d_phi: e_jj and o_jj (rows jj, N - jj; jj = 0, N/2 carry no
+        // S); synthesis: a_jj and b_jj (rows 2 jj - 1, 2 jj; a_0 at row 0, no b_0)
+        const int rx = SYN ? (jj == 0 ? 0 : 2 * jj - 1) : jj;
+        const int ry = SYN ? 2 * jj : ((jj == 0 || jj == half) ? jj : n_ph - jj);
+        const T x = sm[rx * 64 + lane], y = sm[ry * 64 + lane];
+        const T* wr = Ww + jj * 2 * R;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            ac[r] = fma(wr[r], x, ac[r]);
+            as[r] = fma(wr[R + r], y, as[r]);
+        }
+    }
+    if (lane >= nc) return;
+    O* dst = out + (long long)f * n_out * ncol + c0 + lane;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int q = w * R + r;
+        if (MODE == kParAna) {
+            if (q <= m_keep) {
+                dst[(long long)(q == 0 ? 0 : 2 * q - 1) * ncol] = (O)ac[r];
+                if (q > 0) dst[(long long)(2 * q) * ncol] = (O)as[r];
+            }
+        } else if (q <= half) {
+            const T sgn = MODE == kParSyn ? (T)1 : (T)-1;   // f_{N-j} = A - B, y_{N-q} = B - A
+            dst[(long long)q * ncol] = (O)(ac[r] + as[r]);
+            if (q > 0 && q < half) dst[(long long)(n_ph - q) * ncol] = (O)(sgn * (ac[r] - as[r]));
+        }
+    }
+}
+
+template <int R, typename I, typename T, typename O, int MODE>
+__global__ __launch_bounds__(1024) void k_axis_par(const I* __restrict__ in, O* __restrict__ out,
+                                                   const T* __restrict__ Wb, int n_ph, int m_keep, long long ncol) {
+    extern __shared__ double smd[];
+    axis_par_tile<R, I, T, O, MODE>(blockIdx.x, blockIdx.y, in, out, Wb, n_ph, m_keep, ncol, smd);
+}
+
 // The three coordinate derivatives of one run of shells in one launch:
 // b_dr d_r tiles, b_th d_theta tiles and bx_ph column tiles per field of
 // d_phi, interleaved over the grid so that the three kinds run side by side.
@@ -256,17 +398,21 @@ struct D3Dims {
     long long n_lines, n_cols_th, ncol_ph;
     unsigned b_dr, b_th, bx_ph;
     int nf;
-    int R_dr, R_th, R_ph;
+    int R_dr, R_th, R_ph, ph_par;
     int n_r, n_th, n_ph;
 };
 
-constexpr int kFusedMaxR = 9;   // blocked_shape gives R <= 9 for every operator
+// rows per wave the one-launch form is instantiated for: d_r and the parity
+// d_phi up to 9, the circulant d_phi up to 12, the theta tile (four
+// accumulator sets per row) up to 4; the workgroup's registers are the
+// largest case's, so the cases stop at what the tile shapes in use need
+constexpr int kFusedMaxR = 9, kFusedMaxRth = 4, kFusedMaxRcirc = 12;
 
 template <typename T, typename O>
 __global__ __launch_bounds__(1024) void k_derivs3(const double* __restrict__ in, double* __restrict__ out_r,
                                                  O* __restrict__ out_th, O* __restrict__ out_ph,
                                                  const double* __restrict__ Drb, const T* __restrict__ Hsb,
-                                                 const T* __restrict__ Hab, const T* __restrict__ Wph, D3Dims a) {
+                                                 const T* __restrict__ Wph, D3Dims a) {
     extern __shared__ double smd[];
     // the three kinds of tiles interleaved evenly over the grid (Bresenham):
     // block b is the D(b)-th d_r tile if D(b + 1) > D(b), D(b) = floor(b b_dr / B);
@@ -288,17 +434,25 @@ __global__ __launch_bounds__(1024) void k_derivs3(const double* __restrict__ in,
     }
     if (is_th) {
         switch (a.R_th) {
-#define X(R) case R: dtheta_tile<R, T, O>(t_th, in, out_th, Hsb, Hab, a.n_r, a.n_th, a.n_ph, a.n_cols_th, smd); break;
-            X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9)
+#define X(R) case R: dtheta_tile<R, T, O>(t_th, in, out_th, Hsb, a.n_r, a.n_th, a.n_ph, a.n_cols_th, smd); break;
+            X(1) X(2) X(3) X(4)
 #undef X
         }
         return;
     }
     const long long bx = (long long)(t_ph % a.bx_ph);
     const int f = (int)(t_ph / a.bx_ph);
+    if (a.ph_par) {
+        switch (a.R_ph) {
+#define X(R) case R: axis_par_tile<R, double, T, O, kParDphi>(bx, f, in, out_ph, Wph, a.n_ph, 0, a.ncol_ph, smd); break;
+            X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9)
+#undef X
+        }
+        return;
+    }
     switch (a.R_ph) {
 #define X(R) case R: axis_tile<R, double, T, O, true>(bx, f, in, out_ph, Wph, a.n_ph, a.n_ph, a.ncol_ph, 1, smd); break;
-        X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9)
+        X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12)
 #undef X
     }
 }
@@ -366,7 +520,7 @@ hipError_t launch_dr(const KShell& s, const double* in, double* out, int n_field
 }
 
 template <typename T, typename O>
-static hipError_t dtheta_t(const KShell& s, const double* in, O* out, const T* Hsb, const T* Hab, int n_fields,
+static hipError_t dtheta_t(const KShell& s, const double* in, O* out, const T* Hsb, int n_fields,
                            hipStream_t st) {
     const long long n_cols = (long long)n_fields * (s.n_ph / 2) * s.n_r;
     const unsigned blocks = (unsigned)((n_cols + 63) / 64);
@@ -374,7 +528,7 @@ static hipError_t dtheta_t(const KShell& s, const double* in, O* out, const T* H
     const size_t shm = sizeof(T) * 2 * size_t(s.n_th) * 64 + size_t(s.Hth_nw) * 64 * sizeof(double);
     const unsigned nt = 64u * s.Hth_nw;
     switch (s.Hth_R) {
-#define X(R) case R: hipLaunchKernelGGL((k_dtheta<R, T, O>), dim3(blocks), dim3(nt), shm, st, in, out, Hsb, Hab, s.n_r, s.n_th, s.n_ph, n_cols); break;
+#define X(R) case R: hipLaunchKernelGGL((k_dtheta<R, T, O>), dim3(blocks), dim3(nt), shm, st, in, out, Hsb, s.n_r, s.n_th, s.n_ph, n_cols); break;
         SG_R_CASES(X)
 #undef X
         default: return hipErrorInvalidValue;
@@ -383,11 +537,11 @@ static hipError_t dtheta_t(const KShell& s, const double* in, O* out, const T* H
 }
 
 hipError_t launch_dtheta(const KShell& s, const double* in, double* out, int n_fields, hipStream_t st) {
-    return dtheta_t<double, double>(s, in, out, s.Hsb, s.Hab, n_fields, st);
+    return dtheta_t<double, double>(s, in, out, s.Hsb, n_fields, st);
 }
 
 hipError_t launch_dtheta_f32(const KShell& s, const double* in, float* out, int n_fields, hipStream_t st) {
-    return dtheta_t<float, float>(s, in, out, s.Hsb_f, s.Hab_f, n_fields, st);
+    return dtheta_t<float, float>(s, in, out, s.Hsb_f, n_fields, st);
 }
 
 template <typename I, typename T, typename O>
@@ -395,8 +549,30 @@ static hipError_t axis_t(const AxisOp& op, const T* Wb, const I* in, O* out, lon
                          int center, hipStream_t st) {
     if (op.n_in > kAxisMaxIn || 4 * op.passes < kMinWaves) return hipErrorInvalidValue;
     const unsigned bx = (unsigned)((ncol + 63) / 64);
-    const size_t shm = sizeof(T) * size_t(op.n_in) * 64 + size_t(4 * op.passes) * 64 * sizeof(double);
     const unsigned nt = 256u * op.passes;
+    if (op.par) {   // parity form: phi analysis (par 1), synthesis (par 2), d_phi (par 3)
+        const int n_ph = op.par == 2 ? op.n_out : op.n_in;
+        const size_t shm = sizeof(T) * size_t(n_ph) * 64 + size_t(4 * op.passes) * 64 * sizeof(double);
+        switch (op.R) {
+#define X(R)                                                                                                   \
+    case R:                                                                                                    \
+        if (op.par == 1)                                                                                       \
+            hipLaunchKernelGGL((k_axis_par<R, I, T, O, kParAna>), dim3(bx, n_fields), dim3(nt), shm, st, in,   \
+                               out, Wb, n_ph, op.m_keep, ncol);                                                \
+        else if (op.par == 2)                                                                                  \
+            hipLaunchKernelGGL((k_axis_par<R, I, T, O, kParSyn>), dim3(bx, n_fields), dim3(nt), shm, st, in,   \
+                               out, Wb, n_ph, op.m_keep, ncol);                                                \
+        else                                                                                                   \
+            hipLaunchKernelGGL((k_axis_par<R, I, T, O, kParDphi>), dim3(bx, n_fields), dim3(nt), shm, st, in,  \
+                               out, Wb, n_ph, op.m_keep, ncol);                                                \
+        break;
+            SG_R_CASES(X)
+#undef X
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+    const size_t shm = sizeof(T) * size_t(op.n_in) * 64 + size_t(4 * op.passes) * 64 * sizeof(double);
     switch (op.R) {
 #define X(R)                                                                                                   \
     case R:                                                                                                    \
@@ -430,11 +606,11 @@ hipError_t launch_axis_ff(const AxisOp& op, const float* in, float* out, long lo
 }
 
 template <typename T, typename O>
-static hipError_t derivs3_t(const KShell& s, const AxisOp& dph, const T* Wph, const T* Hsb, const T* Hab,
+static hipError_t derivs3_t(const KShell& s, const AxisOp& dph, const T* Wph, const T* Hsb,
                             const double* in, double* out_r, O* out_th, O* out_ph, int n_fields, hipStream_t st) {
     const int nw = s.Dr_nw;
-    if (s.Hth_nw != nw || 4 * dph.passes != nw || !dph.circ || dph.n_in != s.n_ph || s.Dr_R > kFusedMaxR ||
-        s.Hth_R > kFusedMaxR || dph.R > kFusedMaxR)
+    if (s.Hth_nw != nw || 4 * dph.passes != nw || (dph.par != 3 && !dph.circ) || dph.n_in != s.n_ph ||
+        s.Dr_R > kFusedMaxR || s.Hth_R > kFusedMaxRth || dph.R > (dph.circ ? kFusedMaxRcirc : kFusedMaxR))
         return hipErrorNotSupported;   // shapes disagree: the caller launches the three kernels
     if (s.n_th > nw * kThMaxPerThread || dph.n_in > kAxisMaxIn) return hipErrorInvalidValue;
     D3Dims a;
@@ -448,6 +624,7 @@ static hipError_t derivs3_t(const KShell& s, const AxisOp& dph, const T* Wph, co
     a.R_dr = s.Dr_R;
     a.R_th = s.Hth_R;
     a.R_ph = dph.R;
+    a.ph_par = dph.par == 3;
     a.n_r = s.n_r;
     a.n_th = s.n_th;
     a.n_ph = s.n_ph;
@@ -458,20 +635,20 @@ static hipError_t derivs3_t(const KShell& s, const AxisOp& dph, const T* Wph, co
     const unsigned long long blocks = (unsigned long long)a.b_dr + a.b_th + (unsigned long long)a.bx_ph * n_fields;
     if (blocks >= (1ull << 31)) return hipErrorNotSupported;
     hipLaunchKernelGGL((k_derivs3<T, O>), dim3((unsigned)blocks), dim3(64 * nw), shm, st, in, out_r, out_th, out_ph,
-                       s.Drb, Hsb, Hab, Wph, a);
+                       s.Drb, Hsb, Wph, a);
     return hipGetLastError();
 }
 
 hipError_t launch_derivs3(const KShell& s, const AxisOp& dph, const double* in, double* out, int n_fields,
                           hipStream_t st) {
     const long long cnt = (long long)s.npts * n_fields;
-    return derivs3_t<double, double>(s, dph, dph.Wb, s.Hsb, s.Hab, in, out, out + cnt, out + 2 * cnt, n_fields, st);
+    return derivs3_t<double, double>(s, dph, dph.Wb, s.Hsb, in, out, out + cnt, out + 2 * cnt, n_fields, st);
 }
 
 hipError_t launch_derivs3_mixed(const KShell& s, const AxisOp& dph, const double* in, double* dr, float* dang,
                                 int n_fields, hipStream_t st) {
     const long long cnt = (long long)s.npts * n_fields;
-    return derivs3_t<float, float>(s, dph, dph.Wb_f, s.Hsb_f, s.Hab_f, in, dr, dang, dang + cnt, n_fields, st);
+    return derivs3_t<float, float>(s, dph, dph.Wb_f, s.Hsb_f, in, dr, dang, dang + cnt, n_fields, st);
 }
 
 hipError_t launch_chain(const KShell& s, double* du, int n_fields, hipStream_t st) {

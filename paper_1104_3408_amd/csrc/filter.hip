@@ -306,8 +306,6 @@ __global__ __launch_bounds__(256) void k_recompose(KShell s, const TI* __restric
     }
 }
 
-constexpr int kFtPer = 64 / kFiltWaves;   // theta rows one thread stages (N_theta <= 64)
-
 // theta filter, spec[c][q][i][k] -> spec2 (q = 0: a_0; 2m-1: a_m; 2m: b_m).
 // Workgroup (column tile, m, column set, shell of the run): the columns of a
 // set are (group, r_k) pairs, one per lane, all real or all complex and all
@@ -322,8 +320,8 @@ constexpr int kFtPer = 64 / kFiltWaves;   // theta rows one thread stages (N_the
 // two passes of two vectors and half the products of S and D.  Real groups
 // filter a and b with F; at m = 0 a complex group filters a^x and a^y with F
 // (F^n_0 = F^{-n}_0).  J F J v is F applied to v reversed, read back reversed.
-template <int R, typename T>
-__global__ __launch_bounds__(1024) void k_ftheta(int n_r, int n_th, int m_keep, int n_cols_state,
+template <int R, typename T, int NW>
+__global__ __launch_bounds__(64 * NW) void k_ftheta(int n_r, int n_th, int m_keep, int n_cols_state,
                                                 const T* __restrict__ spec, T* __restrict__ spec2,
                                                 const T* __restrict__ Fb, const FiltGroup* __restrict__ groups,
                                                 const FiltSet* __restrict__ sets, int n_sets) {
@@ -343,7 +341,8 @@ __global__ __launch_bounds__(1024) void k_ftheta(int n_r, int n_th, int m_keep, 
     if (c0 >= (long long)fs.count * n_r) return;
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int nw = blockDim.x >> 6;
+    constexpr int nw = NW;
+    constexpr int kFtPer = 64 / NW;   // theta rows one thread stages (N_theta <= 64)
     const long long c = c0 + lane;
     const bool ok = c < (long long)fs.count * n_r;
     const int gi = ok ? (int)(c / n_r) : 0;
@@ -495,20 +494,22 @@ hipError_t launch_recompose_base(const KShell& s, int count, const float* t, con
 template <typename T>
 static hipError_t ftheta_t(const KShell& s, int count, const T* spec, T* spec2, const T* Fb, const FiltPlan& fp,
                            int n_cols, int m_keep, hipStream_t st) {
-    if (fp.R < 1 || fp.R > 16 || kFiltWaves * fp.R < s.n_th) return hipErrorInvalidValue;
+    if (fp.R < 1 || fp.nw * fp.R < s.n_th || s.n_th > 64) return hipErrorInvalidValue;
     const long long cols = (long long)fp.max_groups * s.n_r;
     const dim3 grid((unsigned)((cols + 63) / 64), (unsigned)(m_keep + 1), (unsigned)(fp.n_sets * count));
     const size_t shm = sizeof(T) * 2 * size_t(s.n_th) * 64;
-    switch (fp.R) {
-#define X(R)                                                                                                    \
-    case R:                                                                                                     \
-        hipLaunchKernelGGL((k_ftheta<R, T>), grid, dim3(64 * kFiltWaves), shm, st, s.n_r, s.n_th, m_keep,      \
-                           n_cols, spec, spec2, Fb, fp.groups, fp.sets, fp.n_sets);                             \
-        break;
-        X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
-#undef X
+#define X(W_, R_)                                                                                               \
+    if (fp.nw == W_ && fp.R == R_) {                                                                            \
+        hipLaunchKernelGGL((k_ftheta<R_, T, W_>), grid, dim3(64 * W_), shm, st, s.n_r, s.n_th, m_keep, n_cols, \
+                           spec, spec2, Fb, fp.groups, fp.sets, fp.n_sets);                                     \
+        return hipGetLastError();                                                                               \
     }
-    return hipGetLastError();
+    X(4, 1) X(4, 2) X(4, 3) X(4, 4) X(4, 5) X(4, 6) X(4, 7) X(4, 8) X(4, 9) X(4, 10) X(4, 11) X(4, 12) X(4, 13)
+    X(4, 14) X(4, 15) X(4, 16)
+    X(8, 1) X(8, 2) X(8, 3) X(8, 4) X(8, 5) X(8, 6) X(8, 7) X(8, 8)
+    X(16, 1) X(16, 2) X(16, 3) X(16, 4)
+#undef X
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_ftheta(const KShell& s, int count, const double* spec, double* spec2, const FiltPlan& fp,

@@ -86,28 +86,6 @@ std::vector<double> theta_half_matrix(int n_th) {
     return H;
 }
 
-// Real Fourier analysis (K x n_ph) and synthesis (n_ph x K) for modes
-// m = 0..m_keep, K = 2 m_keep + 1, row order (a_0, a_1, b_1, a_2, b_2, ...)
-// (Sec. 3.1 eqs. Fanalysis, Fsynthesis with J = n_ph; modes above m_keep and
-// the Nyquist mode are not represented).
-void fourier_real_matrices(int n_ph, int m_keep, std::vector<double>& ana, std::vector<double>& syn) {
-    const int K = 2 * m_keep + 1;
-    ana.assign(size_t(K) * n_ph, 0.0);
-    syn.assign(size_t(n_ph) * K, 0.0);
-    for (int j = 0; j < n_ph; ++j) {
-        const double ph = 2.0 * kPi * j / n_ph;
-        ana[j] = 1.0 / n_ph;
-        syn[size_t(j) * K] = 1.0;
-        for (int m = 1; m <= m_keep; ++m) {
-            const double c = std::cos(m * ph), s = std::sin(m * ph);
-            ana[size_t(2 * m - 1) * n_ph + j] = 2.0 * c / n_ph;
-            ana[size_t(2 * m) * n_ph + j] = 2.0 * s / n_ph;
-            syn[size_t(j) * K + 2 * m - 1] = c;
-            syn[size_t(j) * K + 2 * m] = s;
-        }
-    }
-}
-
 // Orthonormal associated Legendre functions with the Condon-Shortley phase,
 // Phat^m_l(cos theta) for 0 <= m <= l <= L, stored at [l][m]:
 // Phat^0_0 = 1/sqrt(4 pi), Phat^m_m = -sqrt((2m+1)/(2m)) sin(theta) Phat^{m-1}_{m-1},

@@ -10,7 +10,6 @@ std::vector<double> phi_points(int n_ph);
 std::vector<double> cheb_matrix(int n, double r_min, double r_max);
 std::vector<double> fourier_column(int n);
 std::vector<double> theta_half_matrix(int n_th);
-void fourier_real_matrices(int n_ph, int m_keep, std::vector<double>& ana, std::vector<double>& syn);
 std::vector<double> spin_synthesis(int n, int m, int n_th, int& K);
 std::vector<double> filter_matrix(int n, int m, int n_th, int n_f);
 }  // namespace sg

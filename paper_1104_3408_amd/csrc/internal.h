@@ -16,12 +16,10 @@ struct KShell {
     int n_r, n_th, n_ph, n_v;
     long long npts;           // N_r N_theta N_phi
     const double* Drb;        // Chebyshev D_r, wave-blocked (see block_operator)
-    const double* Hsb;        // H_L + H_R of the folded theta matrix, wave-blocked
-    const double* Hab;        // H_L - H_R, wave-blocked
+    const double* Hsb;        // theta operator in the equator-parity form of dtheta_tile, wave-blocked
     int Dr_R, Hth_R;          // rows per wave of the blocked d_r / d_theta operators
     int Dr_nw, Hth_nw;        // waves per workgroup of k_dr / k_dtheta
-    const float* Hsb_f;       // FP32 copies for the mixed-precision path
-    const float* Hab_f;
+    const float* Hsb_f;       // FP32 copy for the mixed-precision path
     const double* rk;         // radii
     const double* sth; const double* cth;   // sin, cos theta_i
     const double* sph; const double* cph;   // sin, cos phi_j
@@ -47,7 +45,7 @@ struct FiltPlan {
     const float* Fb_f;          // FP32 copy (mixed-precision filter)
     const FiltGroup* groups;
     const FiltSet* sets;
-    int n_sets, max_groups, R;
+    int n_sets, max_groups, R, nw;   // R rows per wave, nw waves per workgroup
 };
 
 // A matrix applied along the phi axis (n_out x n_in), wave-blocked.
@@ -59,28 +57,30 @@ struct AxisOp {
     // doubled vector dv[t] = v[(t - n) mod n] (zero-padded for padding rows),
     // so the R weights of a wave for input c are dv[n + q0 - c .. + R - 1]
     int circ = 0;
+    // par: the real Fourier analysis (1) or synthesis (2) in the parity form
+    // of axis_par_tile (derivs.hip), keeping orders m <= m_keep; R and passes
+    // then block the row pairs (a_m, b_m), resp. (A_j, B_j), j <= N_phi / 2
+    int par = 0, m_keep = 0;
 };
 
 // Largest number of output rows one wave accumulates, and of waves in one
 // workgroup of the derivative kernels (4 kMaxWaves rows cover n <= 320).
 constexpr int kMaxRows = 20;
 constexpr int kMaxWaves = 16, kMinWaves = 8;
-// Target rows per wave: fewer rows means more waves on one staged tile.
-#ifndef SG_DR_ROWS
-#define SG_DR_ROWS 9
-#endif
-#ifndef SG_TH_ROWS
-#define SG_TH_ROWS 8
-#endif
-#ifndef SG_AXIS_ROWS
-#define SG_AXIS_ROWS 8
-#endif
-constexpr int kDrRows = SG_DR_ROWS, kThRows = SG_TH_ROWS, kAxisRows = SG_AXIS_ROWS;
-// Waves per workgroup of the theta filter (Fb is blocked for this many).
-#ifndef SG_FILT_WAVES
-#define SG_FILT_WAVES 8
-#endif
-constexpr int kFiltWaves = SG_FILT_WAVES;
+// Tile shapes of one shell size: target output rows per wave of the d_r,
+// d_theta, d_phi, phi-analysis and phi-synthesis contractions (fewer rows
+// means more waves on one staged tile, see blocked_shape) and waves per
+// workgroup of the theta filter (4, 8 or 16).  The defaults are the shapes
+// measured best on the 33 x 32 x 64 shell; a table written by the project's
+// autotuner (paper_1104_3408_amd/tune.py) gives them per (N_r, N_theta,
+// n_fields, precision), read by shell_grid_create (tuning.cpp).
+struct Tune {
+    int dr_rows = 9, th_rows = 4, dph_rows = 8, ana_rows = 8, syn_rows = 8, filt_waves = 8;
+    int dph_par = -1;   // d_phi form: 0 circulant window, 1 parity; -1: parity in FP32 modes only
+};
+// The table entry for this shell size, or the defaults; *source names where
+// it came from (the table's path, or "defaults").
+Tune lookup_tuning(int n_r, int n_theta, int n_fields, int precision, std::string* source);
 
 // A contraction operator split into two bfloat16 parts (raw bits), W = hi +
 // lo, zero-padded to [M][K] (M a multiple of 32, K of 16) for the matrix
@@ -96,15 +96,16 @@ struct ShellHost {
     size_t off = 0, count = 0, npts = 0;
     double dt = 0;
     int m_keep = 0, K = 0;
-    double *Drb = nullptr, *Hsb = nullptr, *Hab = nullptr;
-    float *Hsb_f = nullptr, *Hab_f = nullptr;
+    double *Drb = nullptr, *Hsb = nullptr;
+    float *Hsb_f = nullptr;
     int Dr_R = 0, Hth_R = 0, Dr_nw = 0, Hth_nw = 0;
     AxisOp dph, ana, syn;                    // d_phi, Fourier analysis, Fourier synthesis
     Bf3Op bf_dph, bf_hs, bf_ha;              // split d_phi, H_L + H_R, H_L - H_R (BF16X3 only)
     double *rk = nullptr, *sth = nullptr, *cth = nullptr, *sph = nullptr, *cph = nullptr;
     double *Fb = nullptr;                    // theta filter matrices, FiltPlan layout
     float *Fb_f = nullptr;                   // FP32 copy
-    int F_R = 0;                             // theta rows per wave of Fb
+    int F_R = 0, F_nw = 0;                   // theta rows per wave and waves per workgroup of Fb
+    Tune tune;                               // tile shapes of this shell size
     double *H = nullptr, *dH = nullptr;      // static gauge
     bool owns_ops = true;                    // false: operators belong to an earlier identical shell
     std::vector<double> r_host, th_host, ph_host;
