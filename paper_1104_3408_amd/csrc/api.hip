@@ -114,7 +114,8 @@ void free_shell(ShellHost& s) {
         if (p) (void)hipFree(p);
     for (float* p : {s.Hsb_f, s.dph.Wb_f, s.ana.Wb_f, s.syn.Wb_f, s.Fb_f})
         if (p) (void)hipFree(p);
-    for (uint16_t* p : {s.bf_dph.hi, s.bf_dph.lo, s.bf_hs.hi, s.bf_hs.lo, s.bf_ha.hi, s.bf_ha.lo})
+    for (uint16_t* p : {s.bf_dph.hi, s.bf_dph.lo, s.bf_hs.hi, s.bf_hs.lo, s.bf_ha.hi, s.bf_ha.lo, s.bf_ana.hi,
+                        s.bf_ana.lo, s.bf_syn.hi, s.bf_syn.lo, s.bf_F.hi, s.bf_F.lo})
         if (p) (void)hipFree(p);
 }
 
@@ -132,21 +133,24 @@ static float bf16_value(uint16_t h) {
     return x;
 }
 
-// W (n_out x n_in, row-major) split as W = hi + lo in bfloat16 and zero-padded
-// to [M][K] for the matrix-core kernels.
-static hipError_t make_bf3(Bf3Op& op, const std::vector<double>& W, int n_out, int n_in) {
+// W (count matrices of n_out x n_in, row-major, one after the other) split as
+// W = hi + lo in bfloat16 and zero-padded to [count][M][K] for the
+// matrix-core kernels.
+static hipError_t make_bf3(Bf3Op& op, const std::vector<double>& W, int n_out, int n_in, int count = 1) {
     op.n_in = n_in;
     op.n_out = n_out;
     op.K = (n_in + 15) / 16 * 16;
     op.M = (n_out + 31) / 32 * 32;
-    std::vector<uint16_t> hi(size_t(op.M) * op.K, 0), lo(size_t(op.M) * op.K, 0);
-    for (int q = 0; q < n_out; ++q)
-        for (int r = 0; r < n_in; ++r) {
-            const float w = (float)W[size_t(q) * n_in + r];
-            const uint16_t h = bf16_bits(w);
-            hi[size_t(q) * op.K + r] = h;
-            lo[size_t(q) * op.K + r] = bf16_bits(w - bf16_value(h));
-        }
+    const size_t per = size_t(op.M) * op.K;
+    std::vector<uint16_t> hi(per * count, 0), lo(per * count, 0);
+    for (int t = 0; t < count; ++t)
+        for (int q = 0; q < n_out; ++q)
+            for (int r = 0; r < n_in; ++r) {
+                const float w = (float)W[(size_t(t) * n_out + q) * n_in + r];
+                const uint16_t h = bf16_bits(w);
+                hi[per * t + size_t(q) * op.K + r] = h;
+                lo[per * t + size_t(q) * op.K + r] = bf16_bits(w - bf16_value(h));
+            }
     hipError_t e = upload(&op.hi, hi);
     if (e != hipSuccess) return e;
     return upload(&op.lo, lo);
@@ -333,18 +337,25 @@ hipError_t filter_run_split(sg_grid* g, const Run& R, double* u, hipStream_t st)
         e = g->tetrad ? launch_decompose_delta(v, R.count, u, uref, tcol, st) : launch_delta_f32(u, uref, tcol, n, st);
         if (e != hipSuccess) return e;
     }
+    const bool bf3 = g->opt.precision == SG_PREC_BF16X3;   // phi contractions on the matrix cores
     {
         TimeScope ts(g, SG_K_FANA, st);
-        if ((e = launch_axis_ff(S.ana, tcol, spec, ncol, g->n_cols * R.count, st)) != hipSuccess) return e;
+        e = bf3 ? launch_bf3_axis_ff(S.bf_ana, tcol, spec, ncol, g->n_cols * R.count, st)
+                : launch_axis_ff(S.ana, tcol, spec, ncol, g->n_cols * R.count, st);
+        if (e != hipSuccess) return e;
     }
     {
         TimeScope ts(g, SG_K_FTHETA, st);
         const FiltPlan fp{S.Fb, S.Fb_f, g->d_groups, g->d_fsets, (int)g->fsets.size(), g->max_groups, S.F_R, S.F_nw};
-        if ((e = launch_ftheta_f32(v, R.count, spec, spec2, fp, g->n_cols, S.m_keep, st)) != hipSuccess) return e;
+        e = bf3 ? launch_ftheta_bf3(v, R.count, spec, spec2, S.bf_F, fp, g->n_cols, S.m_keep, st)
+                : launch_ftheta_f32(v, R.count, spec, spec2, fp, g->n_cols, S.m_keep, st);
+        if (e != hipSuccess) return e;
     }
     {
         TimeScope ts(g, SG_K_FSYN, st);
-        if ((e = launch_axis_ff(S.syn, spec2, tcol, ncol, g->n_cols * R.count, st)) != hipSuccess) return e;
+        e = bf3 ? launch_bf3_axis_ff(S.bf_syn, spec2, tcol, ncol, g->n_cols * R.count, st)
+                : launch_axis_ff(S.syn, spec2, tcol, ncol, g->n_cols * R.count, st);
+        if (e != hipSuccess) return e;
     }
     TimeScope ts(g, SG_K_RECOMP, st);
     return g->tetrad ? launch_recompose_base(v, R.count, tcol, base, u, st) : launch_add_base(tcol, base, u, n, st);
@@ -452,7 +463,7 @@ sg_status shell_grid_create(const sg_shell_desc* shells, int n_shells, const sg_
             S.Drb = T.Drb; S.Hsb = T.Hsb; S.Hsb_f = T.Hsb_f;
             S.Dr_R = T.Dr_R; S.Hth_R = T.Hth_R; S.Dr_nw = T.Dr_nw; S.Hth_nw = T.Hth_nw;
             S.dph = T.dph; S.ana = T.ana; S.syn = T.syn;
-            S.bf_dph = T.bf_dph; S.bf_hs = T.bf_hs; S.bf_ha = T.bf_ha;
+            S.bf_dph = T.bf_dph; S.bf_hs = T.bf_hs; S.bf_ha = T.bf_ha; S.bf_ana = T.bf_ana; S.bf_syn = T.bf_syn; S.bf_F = T.bf_F;
             S.rk = T.rk; S.sth = T.sth; S.cth = T.cth; S.sph = T.sph; S.cph = T.cph;
             S.Fb = T.Fb; S.Fb_f = T.Fb_f; S.F_R = T.F_R; S.F_nw = T.F_nw;
             S.owns_ops = false;
@@ -470,10 +481,14 @@ sg_status shell_grid_create(const sg_shell_desc* shells, int n_shells, const sg_
         H.F_R = (nt + H.F_nw - 1) / H.F_nw;
         const size_t per_mat = size_t(H.F_nw) * nt * H.F_R;
         std::vector<double> fm(size_t(g->n_sets) * (H.m_keep + 1) * per_mat, 0.0);
+        const bool bf3 = opt->precision == SG_PREC_BF16X3;
+        std::vector<double> fdense(bf3 ? size_t(g->n_sets) * (H.m_keep + 1) * nt * nt : 0);
         for (int k = 0; k < g->n_sets; ++k) {
             const int n = set_spin(g, k), nf = set_nf(g, k);
             for (int m = 0; m <= H.m_keep; ++m) {
                 const std::vector<double> F = filter_matrix(n, m, nt, nf);
+                if (bf3)
+                    std::copy(F.begin(), F.end(), fdense.begin() + (size_t(k) * (H.m_keep + 1) + m) * nt * nt);
                 double* Fb = fm.data() + (size_t(k) * (H.m_keep + 1) + m) * per_mat;
                 for (int w = 0; w < H.F_nw; ++w)
                     for (int ip = 0; ip < nt; ++ip)
@@ -593,8 +608,27 @@ sg_status shell_grid_create(const sg_shell_desc* shells, int n_shells, const sg_
             std::vector<double> Wph(size_t(np_) * np_);
             for (int q = 0; q < np_; ++q)
                 for (int c = 0; c < np_; ++c) Wph[size_t(q) * np_ + c] = fd[((q - c) % np_ + np_) % np_];
+            // dense real Fourier analysis (K x N_phi) and synthesis (N_phi x K) of
+            // the filter, rows a_0, a_1, b_1, ... (Sec. 3.1)
+            std::vector<double> ana(size_t(H.K) * np_), syn(size_t(np_) * H.K);
+            for (int j = 0; j < np_; ++j)
+                for (int m = 0; m <= H.m_keep; ++m) {
+                    const double ang = 2.0 * M_PI * (double)((long long)j * m % np_) / np_;
+                    const double c = std::cos(ang), sn = std::sin(ang);
+                    if (m == 0) {
+                        ana[j] = 1.0 / np_;
+                        syn[size_t(j) * H.K] = 1.0;
+                        continue;
+                    }
+                    ana[size_t(2 * m - 1) * np_ + j] = 2.0 * c / np_;
+                    ana[size_t(2 * m) * np_ + j] = 2.0 * sn / np_;
+                    syn[size_t(j) * H.K + 2 * m - 1] = c;
+                    syn[size_t(j) * H.K + 2 * m] = sn;
+                }
             if (make_bf3(H.bf_dph, Wph, np_, np_) != hipSuccess || make_bf3(H.bf_hs, Hs, nt, nt) != hipSuccess ||
-                make_bf3(H.bf_ha, Ha, nt, nt) != hipSuccess)
+                make_bf3(H.bf_ha, Ha, nt, nt) != hipSuccess || make_bf3(H.bf_ana, ana, H.K, np_) != hipSuccess ||
+                make_bf3(H.bf_syn, syn, np_, H.K) != hipSuccess ||
+                make_bf3(H.bf_F, fdense, nt, nt, g->n_sets * (H.m_keep + 1)) != hipSuccess)
                 return cleanup(SG_ENOMEM, "upload of the split bfloat16 operators failed");
         }
     }

@@ -63,11 +63,13 @@ __device__ __forceinline__ floatx16 mfma3(floatx16 acc, const __bf16* __restrict
     return acc;
 }
 
-// out[f][q][c] = sum_r W[q][r] (in[f][r][c] - m_c), m_c the mean of column c
-// over r (the d_phi contraction with the phi-circle mean removed); column
-// tile `tile` of field f, NW waves.
-template <int NW>
-__device__ __forceinline__ void bf3_axis_tile(long long tile, int f, const double* __restrict__ in,
+// out[f][q][c] = sum_r W[q][r] (in[f][r][c] - m_c) for the 64 columns of
+// tile `tile` of field f, NW waves.  CENTER: m_c is the mean of column c
+// over r (the d_phi contraction with the phi-circle mean removed, FP64
+// input); otherwise m_c = 0 (the phi analysis and synthesis of the filter's
+// FP32 difference columns).
+template <int NW, typename I = double, bool CENTER = true>
+__device__ __forceinline__ void bf3_axis_tile(long long tile, int f, const I* __restrict__ in,
                                               float* __restrict__ out, const __bf16* __restrict__ Whi,
                                               const __bf16* __restrict__ Wlo, int n_in, int n_out, int K, int M,
                                               long long ncol, double* __restrict__ smd) {
@@ -80,23 +82,25 @@ __device__ __forceinline__ void bf3_axis_tile(long long tile, int f, const doubl
     const int nc = (int)min((long long)64, ncol - c0);
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lc = lane < nc ? lane : 0;
-    const double* src = in + (long long)f * n_in * ncol + c0 + lc;
+    const I* src = in + (long long)f * n_in * ncol + c0 + lc;
     constexpr int kPer = kBfMaxIn / NW;
     double v[kPer];
 #pragma unroll
     for (int t = 0; t < kPer; ++t) {
         const int r = w + NW * t;
-        v[t] = (r < n_in) ? src[(long long)r * ncol] : 0.0;
+        v[t] = (r < n_in) ? (double)src[(long long)r * ncol] : 0.0;
     }
-    double part = 0.0;
-#pragma unroll
-    for (int t = 0; t < kPer; ++t) part += v[t];
-    spart[w * 64 + lane] = part;
-    __syncthreads();
     double mc = 0.0;
+    if (CENTER) {
+        double part = 0.0;
 #pragma unroll
-    for (int q = 0; q < NW; ++q) mc += spart[q * 64 + lane];
-    mc /= n_in;
+        for (int t = 0; t < kPer; ++t) part += v[t];
+        spart[w * 64 + lane] = part;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < NW; ++q) mc += spart[q * 64 + lane];
+        mc /= n_in;
+    }
 #pragma unroll
     for (int t = 0; t < kPer; ++t) {
         const int r = w + NW * t;
@@ -231,12 +235,156 @@ __global__ __launch_bounds__(256) void k_bf3_axis(const double* __restrict__ in,
     bf3_axis_tile<4>(blockIdx.x, blockIdx.y, in, out, Whi, Wlo, n_in, n_out, K, M, ncol, smd);
 }
 
+// Fourier analysis / synthesis along phi of the filter's FP32 difference
+// columns (Sec. 3.1), dense split operator: analysis K x N_phi, synthesis
+// N_phi x K.
+__global__ __launch_bounds__(256) void k_bf3_axis_ff(const float* __restrict__ in, float* __restrict__ out,
+                                                     const __bf16* __restrict__ Whi, const __bf16* __restrict__ Wlo,
+                                                     int n_in, int n_out, int K, int M, long long ncol) {
+    extern __shared__ double smd[];
+    bf3_axis_tile<4, float, false>(blockIdx.x, blockIdx.y, in, out, Whi, Wlo, n_in, n_out, K, M, ncol, smd);
+}
+
 __global__ __launch_bounds__(256) void k_bf3_theta(const double* __restrict__ in, float* __restrict__ out,
                                                    const __bf16* __restrict__ Shi, const __bf16* __restrict__ Slo,
                                                    const __bf16* __restrict__ Ahi, const __bf16* __restrict__ Alo,
                                                    int n_r, int n_th, int n_ph, int K, int M, long long n_cols) {
     extern __shared__ double smd[];
     bf3_theta_tile<4>(blockIdx.x, in, out, Shi, Slo, Ahi, Alo, n_r, n_th, n_ph, K, M, n_cols, smd);
+}
+
+// Theta filter of the split filter's FP32 spectral columns on the matrix
+// cores (SG_PREC_BF16X3).  Same workgroups and combinations as k_ftheta
+// (filter.hip): a column tile of one column set at order m; for a complex
+// group at m > 0 two passes, P = F_+ (a^x + b^y), M = F_- (a^x - b^y) and
+// P = F_- (a^y + b^x), M = F_+ (a^y - b^x), with F_- = J F_+ J applied as F_+
+// on theta-reversed vectors (J reverses theta).  The two vectors of a pass
+// are staged split (hi, lo bfloat16) and transposed, [column][K + pad], F is
+// F^{|n|}_m split and zero-padded to [M][K]; four waves form the 32 x 32
+// blocks of F v0 and F v1, which go through LDS (FP32) for the reversal on
+// the way out.
+__global__ __launch_bounds__(256) void k_ftheta_bf3(int n_r, int n_th, int m_keep, int n_cols_state,
+                                                    const float* __restrict__ spec, float* __restrict__ spec2,
+                                                    const __bf16* __restrict__ Fhi, const __bf16* __restrict__ Flo,
+                                                    int K, int M, const FiltGroup* __restrict__ groups,
+                                                    const FiltSet* __restrict__ sets, int n_sets) {
+    extern __shared__ double smd[];
+    const int ldx = K + kBfPad;
+    __bf16* x0h = reinterpret_cast<__bf16*>(smd);   // [64][ldx] each
+    __bf16* x0l = x0h + 64 * ldx;
+    __bf16* x1h = x0l + 64 * ldx;
+    __bf16* x1l = x1h + 64 * ldx;
+    float* res = reinterpret_cast<float*>(x1l + 64 * ldx);   // [2][n_th][64]
+    const int m = blockIdx.y;
+    const FiltSet fs = sets[blockIdx.z % n_sets];
+    const int shell = blockIdx.z / n_sets;
+    const long long per_m = (long long)n_th * n_r;
+    const long long col = (long long)(2 * m_keep + 1) * per_m;   // one storage column
+    {
+        const long long so = (long long)shell * n_cols_state * col;
+        spec += so;
+        spec2 += so;
+    }
+    const long long c0 = (long long)blockIdx.x * 64;
+    if (c0 >= (long long)fs.count * n_r) return;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    constexpr int NW = 4, kPer = 64 / NW;   // theta rows one thread stages (N_theta <= 64)
+    const long long c = c0 + lane;
+    const bool ok = c < (long long)fs.count * n_r;
+    const int gi = ok ? (int)(c / n_r) : 0;
+    const int k = ok ? (int)(c - (long long)gi * n_r) : 0;
+    const FiltGroup G = groups[fs.first + gi];
+    const int qa = (m == 0) ? 0 : 2 * m - 1, qb = 2 * m;
+    const long long fo = (long long)(fs.mat * (m_keep + 1) + m) * M * K;
+    const __bf16* Wh = Fhi + fo;
+    const __bf16* Wl = Flo + fo;
+    const bool mix = fs.cplx && m > 0;   // block-uniform
+    const bool neg = G.sign < 0;          // F_+ = J F J for a negative spin
+    for (int pass = 0; pass < (mix ? 2 : 1); ++pass) {
+        const float* xa;
+        const float* xb = nullptr;
+        bool rev0 = false, rev1 = false;
+        if (!fs.cplx) {
+            xa = spec + G.re * col + qa * per_m + k;
+            if (m > 0) xb = spec + G.re * col + qb * per_m + k;
+        } else if (m == 0) {
+            xa = spec + G.re * col + k;
+            xb = spec + G.im * col + k;
+        } else if (pass == 0) {
+            xa = spec + G.re * col + qa * per_m + k;
+            xb = spec + G.im * col + qb * per_m + k;
+            rev0 = neg;
+            rev1 = !neg;
+        } else {
+            xa = spec + G.im * col + qa * per_m + k;
+            xb = spec + G.re * col + qb * per_m + k;
+            rev0 = !neg;
+            rev1 = neg;
+        }
+        float la[kPer], lb[kPer];
+#pragma unroll
+        for (int t = 0; t < kPer; ++t) {
+            const int ip = w + NW * t;
+            la[t] = (ip < n_th) ? xa[ip * (long long)n_r] : 0.0f;
+            lb[t] = (ip < n_th && xb) ? xb[ip * (long long)n_r] : 0.0f;
+        }
+        if (pass > 0) __syncthreads();
+#pragma unroll
+        for (int t = 0; t < kPer; ++t) {
+            const int ip = w + NW * t;
+            if (ip < K) {   // rows n_th .. K - 1 are zero padding of the contraction
+                __bf16 h0 = (__bf16)0.0f, l0 = (__bf16)0.0f, h1 = (__bf16)0.0f, l1 = (__bf16)0.0f;
+                int r0 = ip, r1 = ip;
+                if (ip < n_th) {
+                    const float va = ok ? la[t] : 0.0f, vb = ok ? lb[t] : 0.0f;
+                    split_bf16(mix ? va + vb : va, h0, l0);
+                    split_bf16(mix ? va - vb : vb, h1, l1);
+                    r0 = rev0 ? n_th - 1 - ip : ip;
+                    r1 = rev1 ? n_th - 1 - ip : ip;
+                }
+                x0h[lane * ldx + r0] = h0;
+                x0l[lane * ldx + r0] = l0;
+                x1h[lane * ldx + r1] = h1;
+                x1l[lane * ldx + r1] = l1;
+            }
+        }
+        __syncthreads();
+        const int blocks = (M / 32) * 2 * 2;   // row blocks x column blocks x (v0, v1)
+        for (int b = w; b < blocks; b += NW) {
+            const int vec = b & 1, nb = (b >> 1) & 1, mb = b >> 2;
+            floatx16 acc;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+            acc = mfma3(acc, Wh, Wl, vec ? x1h : x0h, vec ? x1l : x0l, K, ldx, mb, nb, lane);
+            const int cc = 32 * nb + (lane & 31);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int q = 32 * mb + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+                if (q < n_th) res[(vec * n_th + q) * 64 + cc] = acc[i];
+            }
+        }
+        __syncthreads();
+        if (!ok) continue;
+        for (int i = w; i < n_th; i += NW) {
+            const float p0 = res[(rev0 ? n_th - 1 - i : i) * 64 + lane];
+            const float p1 = res[(n_th + (rev1 ? n_th - 1 - i : i)) * 64 + lane];
+            const long long o = (long long)i * n_r + k;
+            if (!fs.cplx) {
+                spec2[G.re * col + qa * per_m + o] = p0;
+                if (m > 0) spec2[G.re * col + qb * per_m + o] = p1;
+            } else if (m == 0) {
+                spec2[G.re * col + o] = p0;
+                spec2[G.im * col + o] = p1;
+            } else if (pass == 0) {
+                spec2[G.re * col + qa * per_m + o] = 0.5f * (p0 + p1);   // a^x'
+                spec2[G.im * col + qb * per_m + o] = 0.5f * (p0 - p1);   // b^y'
+            } else {
+                spec2[G.im * col + qa * per_m + o] = 0.5f * (p0 + p1);   // a^y'
+                spec2[G.re * col + qb * per_m + o] = 0.5f * (p0 - p1);   // b^x'
+            }
+        }
+    }
 }
 
 // One launch for a stage's three contractions in SG_PREC_BF16X3 (the FP64
@@ -325,6 +473,28 @@ hipError_t launch_bf3_dphi(const KShell& s, const Bf3Op& op, const double* in, f
     if (op.n_in > kBfMaxIn || op.K < op.n_in || op.K % 16 || op.M % 32 || op.M < op.n_out || op.M > 128)
         return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_bf3_axis, dim3((unsigned)((ncol + 63) / 64), (unsigned)n_fields), dim3(256),
+                       bf3_axis_shm(op.K), st, in, out, reinterpret_cast<const __bf16*>(op.hi),
+                       reinterpret_cast<const __bf16*>(op.lo), op.n_in, op.n_out, op.K, op.M, ncol);
+    return hipGetLastError();
+}
+
+hipError_t launch_ftheta_bf3(const KShell& s, int count, const float* spec, float* spec2, const Bf3Op& F,
+                             const FiltPlan& fp, int n_cols, int m_keep, hipStream_t st) {
+    if (s.n_th > 64 || F.K < s.n_th || F.K % 16 || F.M % 32 || F.M < s.n_th || F.M > 64) return hipErrorInvalidValue;
+    const long long cols = (long long)fp.max_groups * s.n_r;
+    const dim3 grid((unsigned)((cols + 63) / 64), (unsigned)(m_keep + 1), (unsigned)(fp.n_sets * count));
+    const size_t shm = 4 * size_t(64) * (F.K + kBfPad) * sizeof(__bf16) + 2 * size_t(s.n_th) * 64 * sizeof(float);
+    hipLaunchKernelGGL(k_ftheta_bf3, grid, dim3(256), shm, st, s.n_r, s.n_th, m_keep, n_cols, spec, spec2,
+                       reinterpret_cast<const __bf16*>(F.hi), reinterpret_cast<const __bf16*>(F.lo), F.K, F.M,
+                       fp.groups, fp.sets, fp.n_sets);
+    return hipGetLastError();
+}
+
+hipError_t launch_bf3_axis_ff(const Bf3Op& op, const float* in, float* out, long long ncol, int n_fields,
+                              hipStream_t st) {
+    if (op.n_in > kBfMaxIn || op.K < op.n_in || op.K % 16 || op.M % 32 || op.M < op.n_out || op.M > 128)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_bf3_axis_ff, dim3((unsigned)((ncol + 63) / 64), (unsigned)n_fields), dim3(256),
                        bf3_axis_shm(op.K), st, in, out, reinterpret_cast<const __bf16*>(op.hi),
                        reinterpret_cast<const __bf16*>(op.lo), op.n_in, op.n_out, op.K, op.M, ncol);
     return hipGetLastError();

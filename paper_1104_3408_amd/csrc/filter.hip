@@ -247,23 +247,17 @@ __global__ __launch_bounds__(64 * kDecParts) void k_decompose(KShell s, const do
 }
 
 // With base, u = base + (recomposed columns) (base: the filtered reference).
+// Each block of fields (g and Pi, then Phi) is recombined into registers
+// first; then the block's base values are loaded together and the sums
+// stored, so a store does not wait on its own base load one at a time.
 template <typename TI>
 __global__ __launch_bounds__(256) void k_recompose(KShell s, const TI* __restrict__ t, const double* __restrict__ base,
                                                    double* __restrict__ u_) {
     const long long np = s.npts;
     const long long so = (long long)blockIdx.y * s.n_v * np;   // shell of a run
     t += so;
-    struct Dst {
-        double* a;
-        const double* b;
-        struct Ref {
-            double* a;
-            const double* b;
-            long long k;
-            __device__ void operator=(double v) const { a[k] = b ? b[k] + v : v; }
-        };
-        __device__ Ref operator[](long long k) const { return Ref{a, b, k}; }
-    } u{u_ + so, base ? base + so : nullptr};
+    double* __restrict__ u = u_ + so;
+    const double* __restrict__ bs = base ? base + so : nullptr;
     const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np) return;
     const int i = (int)((p / s.n_r) % s.n_th);
@@ -271,38 +265,72 @@ __global__ __launch_bounds__(256) void k_recompose(KShell s, const TI* __restric
     const Tetrad e = make_tetrad(s, i, j);
     auto get = [&](int c) { return (double)t[(long long)c * np + p]; };
     auto getc = [&](int c) { return cx{get(c), get(c + 1)}; };
-    for (int blk = 0; blk < 2; ++blk) {
-        const int o = 10 * blk;
-        Sym2 c;
-        c.tt = get(o); c.tr = get(o + 1); c.rr = get(o + 2); c.mmb = get(o + 3);
-        c.tm = getc(o + 4); c.rm = getc(o + 6); c.mm = getc(o + 8);
-        cx M[4][4];
-        recomp_cx(sym2_to_cx10(c), e, M);
-        for (int a = 0; a < 4; ++a)
-            for (int b = a; b < 4; ++b) u[(long long)(o + pr(a, b)) * np + p] = M[a][b].re;
-    }
-    Sym2 cr;
-    cr.tt = get(20); cr.tr = get(21); cr.rr = get(22); cr.mmb = get(23);
-    cr.tm = getc(24); cr.rm = getc(26); cr.mm = getc(28);
-    cx R[4][4], M[4][4];
-    recomp_cx(sym2_to_cx10(cr), e, R);
-    Cx10 cm{getc(30), getc(32), getc(34), getc(36), getc(38), getc(40), getc(42), getc(44), getc(48), getc(46)};
-    recomp_cx(cm, e, M);
-    for (int x = 0; x < 3; ++x)
-        for (int a = 0; a < 4; ++a)
-            for (int b = a; b < 4; ++b) {
-                // Phi_x = rhat_x R + mbar_x M + m_x conj(M)
-                const cx v = e.mb[x] * M[a][b];
-                u[(long long)(20 + 10 * x + pr(a, b)) * np + p] = e.r[x] * R[a][b].re + 2.0 * v.re;
-            }
-    if (s.n_v == 58) {
-        for (int blk = 0; blk < 2; ++blk) {
-            const int o = 50 + 4 * blk;
-            const double v0 = get(o), vr = get(o + 1);
-            const cx vm = getc(o + 2);
-            u[(long long)o * np + p] = v0;
-            for (int x = 0; x < 3; ++x) u[(long long)(o + 1 + x) * np + p] = vr * e.r[x] + 2.0 * (vm * e.mb[x]).re;
+    // store fields first .. first + n - 1 from vo, adding the base when present
+    auto flush = [&](const double* vo, int first, int n) {
+        if (bs) {
+            double vb[30];
+#pragma unroll
+            for (int f = 0; f < 30; ++f)
+                if (f < n) vb[f] = bs[(long long)(first + f) * np + p];
+#pragma unroll
+            for (int f = 0; f < 30; ++f)
+                if (f < n) u[(long long)(first + f) * np + p] = vb[f] + vo[f];
+        } else {
+#pragma unroll
+            for (int f = 0; f < 30; ++f)
+                if (f < n) u[(long long)(first + f) * np + p] = vo[f];
         }
+    };
+    {
+        double vo[20];
+#pragma unroll
+        for (int blk = 0; blk < 2; ++blk) {
+            const int o = 10 * blk;
+            Sym2 c;
+            c.tt = get(o); c.tr = get(o + 1); c.rr = get(o + 2); c.mmb = get(o + 3);
+            c.tm = getc(o + 4); c.rm = getc(o + 6); c.mm = getc(o + 8);
+            cx M[4][4];
+            recomp_cx(sym2_to_cx10(c), e, M);
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = a; b < 4; ++b) vo[o + pr(a, b)] = M[a][b].re;
+        }
+        flush(vo, 0, 20);
+    }
+    {
+        double vo[30];
+        Sym2 cr;
+        cr.tt = get(20); cr.tr = get(21); cr.rr = get(22); cr.mmb = get(23);
+        cr.tm = getc(24); cr.rm = getc(26); cr.mm = getc(28);
+        cx R[4][4], M[4][4];
+        recomp_cx(sym2_to_cx10(cr), e, R);
+        Cx10 cm{getc(30), getc(32), getc(34), getc(36), getc(38), getc(40), getc(42), getc(44), getc(48), getc(46)};
+        recomp_cx(cm, e, M);
+#pragma unroll
+        for (int x = 0; x < 3; ++x)
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = a; b < 4; ++b) {
+                    // Phi_x = rhat_x R + mbar_x M + m_x conj(M)
+                    const cx v = e.mb[x] * M[a][b];
+                    vo[10 * x + pr(a, b)] = e.r[x] * R[a][b].re + 2.0 * v.re;
+                }
+        flush(vo, 20, 30);
+    }
+    if (s.n_v == 58) {
+        double vo[8];
+#pragma unroll
+        for (int blk = 0; blk < 2; ++blk) {
+            const int o = 4 * blk;
+            const double v0 = get(50 + o), vr = get(51 + o);
+            const cx vm = getc(52 + o);
+            vo[o] = v0;
+#pragma unroll
+            for (int x = 0; x < 3; ++x) vo[o + 1 + x] = vr * e.r[x] + 2.0 * (vm * e.mb[x]).re;
+        }
+        flush(vo, 50, 8);
     }
 }
 

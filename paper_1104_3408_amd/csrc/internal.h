@@ -101,6 +101,8 @@ struct ShellHost {
     int Dr_R = 0, Hth_R = 0, Dr_nw = 0, Hth_nw = 0;
     AxisOp dph, ana, syn;                    // d_phi, Fourier analysis, Fourier synthesis
     Bf3Op bf_dph, bf_hs, bf_ha;              // split d_phi, H_L + H_R, H_L - H_R (BF16X3 only)
+    Bf3Op bf_ana, bf_syn;                    // split phi analysis / synthesis of the filter (BF16X3 only)
+    Bf3Op bf_F;                              // split theta filters F^{|n|}_m, [set][m][M][K] (BF16X3 only)
     double *rk = nullptr, *sth = nullptr, *cth = nullptr, *sph = nullptr, *cph = nullptr;
     double *Fb = nullptr;                    // theta filter matrices, FiltPlan layout
     float *Fb_f = nullptr;                   // FP32 copy
@@ -202,6 +204,14 @@ std::vector<double> block_operator(const std::vector<double>& W, int n_out, int 
 int blocked_shape(int n_out, int target, int& R, int& passes);
 hipError_t launch_bf3_dphi(const KShell& s, const Bf3Op& op, const double* in, float* out, int n_fields,
                            hipStream_t st);
+// Theta filter of FP32 spectral columns on the matrix cores (F: the split
+// filter matrices of every column set and order m).
+hipError_t launch_ftheta_bf3(const KShell& s, int count, const float* spec, float* spec2, const Bf3Op& F,
+                             const FiltPlan& fp, int n_cols, int m_keep, hipStream_t st);
+// Fourier analysis / synthesis of FP32 columns along phi on the matrix cores
+// (dense split operator, n_fields blocks of ncol columns).
+hipError_t launch_bf3_axis_ff(const Bf3Op& op, const float* in, float* out, long long ncol, int n_fields,
+                              hipStream_t st);
 hipError_t launch_bf3_dtheta(const KShell& s, const Bf3Op& hs, const Bf3Op& ha, const double* in, float* out,
                              int n_fields, hipStream_t st);
 // d_r (FP64, into dr) and the BF16x3 d_theta, d_phi (FP32, into dang) in one
