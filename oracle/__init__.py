@@ -21,6 +21,10 @@ Modules (each function cites the section/equation it follows):
   initial_data  Kerr-Schild data with numerical Phi, Pi and static gauge (App. A.3)
   evolve        classical RK4 method of lines with the filter after each step
                 (Sec. 2.5)
+  nested        shells coupled at shared spheres by characteristic upwinding
+                (reading of the outlook of Sec. 1 / Sec. 5 with App. A.2)
+  rounding      the angular products in the rounding of the reduced-precision
+                modes (FP32, BF16x3 split products, plain bfloat16)
 
 Parity pins: every function is checked in ``tests/test_oracle_*.py`` against
 values the paper prints, closed forms, invariants or brute force.  The only
