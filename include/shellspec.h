@@ -59,7 +59,7 @@ typedef enum {
 enum { SG_FILTER_YN = 0, SG_FILTER_Y = 1, SG_FILTER_YG = 2, SG_FILTER_NONE = 3 };
 enum { SG_PREC_FP64 = 0, SG_PREC_FP32 = 1, SG_PREC_BF16X3 = 2 };
 enum { SG_COORD = 0, SG_CART = 1 };
-enum { SG_CHECK_FINITE = 1u, SG_NO_GRAPH = 2u };
+enum { SG_CHECK_FINITE = 1u, SG_NO_GRAPH = 2u, SG_NESTED = 4u };
 
 /* One shell: N_r Chebyshev points on [r_min, r_max], N_theta x N_phi angles
  * (Sec. 2.1).  Requirements checked by shell_grid_create: 4 <= N_r <= 80,
@@ -92,7 +92,15 @@ typedef struct {
     double mass;      /* black-hole mass M used by sg_kerr_schild_data */
     unsigned flags;   /* SG_CHECK_FINITE: rk_step reports NaN/Inf; SG_NO_GRAPH: rk_step
                          launches every kernel itself instead of replaying a captured
-                         HIP graph of one step */
+                         HIP graph of one step; SG_NESTED: consecutive shells whose
+                         radii meet (r_max of one = r_min of the next) are coupled at
+                         the shared sphere (each keeps a copy of it; both copies get
+                         one right-hand side, every characteristic field of App. A.2
+                         taken from the side it travels from, the mean for speed 0:
+                         the paper's outlook of nested shells, Sec. 1 and Sec. 5, whose
+                         interface condition it leaves open); such shells must have
+                         the same N_theta and N_phi (else SG_ESHAPE) and one time step
+                         (the smaller Courant step of the chain by default) */
 } sg_options;
 
 /* Build the grid object for n_shells shells: collocation points, the 1-d

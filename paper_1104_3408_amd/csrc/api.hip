@@ -370,8 +370,11 @@ std::vector<Run> make_runs(const sg_grid* g, const double* dts) {
         if (!runs.empty()) {
             const int f = runs.back().first;
             const sg_shell_desc& e = g->sh[f].d;
+            // shells at an interface of nested shells run alone (their kernels
+            // store the interface's raw right-hand sides)
             join = d.n_r == e.n_r && d.n_theta == e.n_theta && d.n_phi == e.n_phi && d.r_min == e.r_min &&
-                   d.r_max == e.r_max && (!dts || dts[s] == dts[f]);
+                   d.r_max == e.r_max && (!dts || dts[s] == dts[f]) && !g->sh[s].kraw_out && !g->sh[s].kraw_in &&
+                   !g->sh[f].kraw_out && !g->sh[f].kraw_in;
         }
         if (join)
             runs.back().count++;
@@ -398,6 +401,7 @@ KShell ShellHost::view(int n_v) const {
     k.Hth_R = Hth_R;
     k.Dr_nw = Dr_nw;
     k.Hth_nw = Hth_nw;
+    k.th_plane = th_plane;
     k.Hsb_f = Hsb_f;
     k.rk = rk;
     k.sth = sth;
@@ -406,6 +410,8 @@ KShell ShellHost::view(int n_v) const {
     k.cph = cph;
     k.H = H;
     k.dH = dH;
+    k.kraw_out = kraw_out;
+    k.kraw_in = kraw_in;
     return k;
 }
 
@@ -462,6 +468,7 @@ sg_status shell_grid_create(const sg_shell_desc* shells, int n_shells, const sg_
             const ShellHost& T = g->sh[twin];
             S.Drb = T.Drb; S.Hsb = T.Hsb; S.Hsb_f = T.Hsb_f;
             S.Dr_R = T.Dr_R; S.Hth_R = T.Hth_R; S.Dr_nw = T.Dr_nw; S.Hth_nw = T.Hth_nw;
+            S.th_plane = T.th_plane;
             S.dph = T.dph; S.ana = T.ana; S.syn = T.syn;
             S.bf_dph = T.bf_dph; S.bf_hs = T.bf_hs; S.bf_ha = T.bf_ha; S.bf_ana = T.bf_ana; S.bf_syn = T.bf_syn; S.bf_F = T.bf_F;
             S.rk = T.rk; S.sth = T.sth; S.cth = T.cth; S.sph = T.sph; S.cph = T.cph;
@@ -512,6 +519,9 @@ sg_status shell_grid_create(const sg_shell_desc* shells, int n_shells, const sg_
             return cleanup(SG_ESHAPE, "radial or theta operator too large for one workgroup");
         H.Dr_nw = 4 * passes;
         H.Hth_nw = 4 * passes_th;
+        // the plane tile stages two N_theta x N_r planes: within the LDS of one workgroup
+        H.th_plane = H.tune.th_plane && opt->precision == SG_PREC_FP64 &&
+                     sizeof(double) * (2 * size_t(nt) * nr + size_t(H.Hth_nw) * nr) <= kMaxLdsBytes;
         std::vector<double> Drb = block_operator(cheb_matrix(nr, H.d.r_min, H.d.r_max), nr, nr, H.Dr_R, passes);
         // equator-parity form of Hs and Ha (dtheta_tile): for rows i < hh and
         // inputs i' < hh, Q = (M_ii' + M_i,N-1-i') / 2 and P = (M_ii' - M_i,N-1-i') / 2
@@ -633,6 +643,30 @@ sg_status shell_grid_create(const sg_shell_desc* shells, int n_shells, const sg_
         }
     }
     g->total = off;
+    if (opt->flags & SG_NESTED) {   // shells coupled at shared spheres (reading of Sec. 1 / Sec. 5)
+        for (int s = 0; s + 1 < n_shells; ++s) {
+            ShellHost &A = g->sh[s], &B = g->sh[s + 1];
+            if (A.d.r_max != B.d.r_min) continue;
+            if (A.d.n_theta != B.d.n_theta || A.d.n_phi != B.d.n_phi)
+                return cleanup(SG_ESHAPE, "nested shells must share the angular grid of their common sphere");
+            Interface I;
+            I.a = s;
+            const size_t n = size_t(opt->n_fields) * A.d.n_theta * A.d.n_phi;
+            if (hipMalloc((void**)&I.kraw, sizeof(double) * 2 * n) != hipSuccess)
+                return cleanup(SG_ENOMEM, "interface workspace allocation failed");
+            g->ifaces.push_back(I);
+            A.kraw_out = I.kraw;
+            B.kraw_in = I.kraw + n;
+        }
+        // one time step for every chain of coupled shells: the smallest
+        for (size_t c = 0; c < g->sh.size();) {
+            size_t e = c;
+            double m = g->sh[c].dt;
+            while (e + 1 < g->sh.size() && g->sh[e].kraw_out) m = std::min(m, g->sh[++e].dt);
+            for (size_t t = c; t <= e; ++t) g->sh[t].dt = m;
+            c = e + 1;
+        }
+    }
     g->runs = make_runs(g, nullptr);
     size_t maxc = 0;
     spec = 0;
@@ -698,6 +732,8 @@ static void drop_graph(sg_grid* g);
 void shell_grid_destroy(sg_grid* g) {
     if (!g) return;
     drop_graph(g);
+    for (auto& I : g->ifaces)
+        if (I.kraw) (void)hipFree(I.kraw);
     if (g->cap) (void)hipStreamDestroy(g->cap);
     for (auto sd : g->side)
         if (sd) (void)hipStreamDestroy(sd);
@@ -787,6 +823,9 @@ sg_status ghg_constraints(sg_grid* g, const double* u, double* norms, sg_stream_
     return SG_OK;
 }
 
+static hipError_t patch_interface(sg_grid* g, const Interface& I, double* u, double* out, double dt, int stage,
+                                  hipStream_t st);
+
 sg_status ghg_rhs(sg_grid* g, const double* u, const double* du_cart, double* rhs, sg_stream_t stream) {
     if (!g || !u || !rhs) return fail(SG_EINVAL, "NULL argument");
     if ((const double*)rhs == u) return fail(SG_EINVAL, "rhs must not alias u");
@@ -799,6 +838,7 @@ sg_status ghg_rhs(sg_grid* g, const double* u, const double* du_cart, double* rh
         TimeScope ts(g, SG_K_RHS, st);
         HIP_TRY(launch_rhs(v, 1, u + S.off, d, du_cart != nullptr, rhs + S.off, nullptr, nullptr, 0.0, 0, st));
     }
+    for (const Interface& I : g->ifaces) HIP_TRY(patch_interface(g, I, const_cast<double*>(u), rhs, 0.0, 0, st));
     return SG_OK;
 }
 
@@ -813,49 +853,87 @@ static bool run_fits(const sg_grid* g, const Run& R) {
     return S.off + n <= g->total && n <= g->tcol_size && spec <= g->spec_size;
 }
 
-// One filtered RK4 step of every shell (Sec. 2.5): stage inputs u -> a -> b -> a,
-// the fourth stage writes u; then the filter.
-static hipError_t step_launches(sg_grid* g, double* u, const double* dt, hipStream_t st, bool fork) {
+// Stage `stage` (1..4) of one run of shells (Sec. 2.5): stage inputs u -> a ->
+// b -> a, the fourth stage writes u.
+static hipError_t run_stage(sg_grid* g, const Run& R, double* u, const double* dt, int stage, hipStream_t st,
+                            bool fork) {
     const int nv = g->opt.n_fields;
-    double* usA = g->us;
-    double* usB = g->us + g->total;
+    const ShellHost& S = g->sh[R.first];
+    const KShell v = S.view(nv);
+    const double h = dt[R.first];
+    const int nvr = nv * R.count;                 // variables of the whole run
+    double* u0 = u + S.off;
+    double* a = g->us + S.off;
+    double* b = g->us + g->total + S.off;
+    double* ac = g->acc + S.off;
+    const double* in[4] = {u0, a, b, a};
+    double* outp[4] = {a, b, a, u0};
     hipError_t e;
-    for (const Run& R : make_runs(g, dt)) {
-        const ShellHost& S = g->sh[R.first];
-        const KShell v = S.view(nv);
-        const double h = dt[R.first];
-        if (!run_fits(g, R)) return hipErrorInvalidValue;
-        const int nvr = nv * R.count;                 // variables of the whole run
-        double* u0 = u + S.off;
-        double* a = usA + S.off;
-        double* b = usB + S.off;
-        double* ac = g->acc + S.off;
-        const double* in[4] = {u0, a, b, a};
-        double* outp[4] = {a, b, a, u0};
-        const bool mixed = g->opt.precision != SG_PREC_FP64;
+    if (g->opt.precision != SG_PREC_FP64) {
         float* dang = reinterpret_cast<float*>(g->dbuf + S.count * R.count);
-        for (int stage = 1; stage <= 4; ++stage) {
-            if (mixed) {
-                if ((e = derivs_shell_mixed(g, R.first, in[stage - 1], g->dbuf, dang, nvr, st, fork)) != hipSuccess)
-                    return e;
-                TimeScope ts(g, SG_K_RHS, st);
-                if ((e = launch_rhs_mixed(v, R.count, in[stage - 1], g->dbuf, dang, outp[stage - 1], u0, ac, h,
-                                          stage, st)) != hipSuccess)
-                    return e;
-            } else {
-                if ((e = derivs_shell(g, R.first, in[stage - 1], g->dbuf, nvr, false, st, fork)) != hipSuccess)
-                    return e;
-                TimeScope ts(g, SG_K_RHS, st);
-                if ((e = launch_rhs(v, R.count, in[stage - 1], g->dbuf, false, outp[stage - 1], u0, ac, h, stage,
-                                    st)) != hipSuccess)
-                    return e;
-            }
-        }
-        if (g->opt.filter_kind != SG_FILTER_NONE) {
-            e = mixed ? filter_run_split(g, R, u0, st) : filter_run(g, R, u0, st);
-            if (e != hipSuccess) return e;
-        }
+        if ((e = derivs_shell_mixed(g, R.first, in[stage - 1], g->dbuf, dang, nvr, st, fork)) != hipSuccess) return e;
+        TimeScope ts(g, SG_K_RHS, st);
+        return launch_rhs_mixed(v, R.count, in[stage - 1], g->dbuf, dang, outp[stage - 1], u0, ac, h, stage, st);
     }
+    if ((e = derivs_shell(g, R.first, in[stage - 1], g->dbuf, nvr, false, st, fork)) != hipSuccess) return e;
+    TimeScope ts(g, SG_K_RHS, st);
+    return launch_rhs(v, R.count, in[stage - 1], g->dbuf, false, outp[stage - 1], u0, ac, h, stage, st);
+}
+
+// Interface I of nested shells after stage `stage` (1..4) of rk_step on the
+// state u: the common right-hand side of the two copies of the shared sphere
+// replaces the raw ones in the copies' stage outputs and accumulators.
+// Stage 0 (ghg_rhs): u is the state and out the right-hand side array.
+static hipError_t patch_interface(sg_grid* g, const Interface& I, double* u, double* out, double dt, int stage,
+                                  hipStream_t st) {
+    const ShellHost &A = g->sh[I.a], &B = g->sh[I.a + 1];
+    const int nv = g->opt.n_fields;
+    const size_t n = size_t(nv) * A.d.n_theta * A.d.n_phi;
+    const double* in_s = u;
+    double* out_s = out;
+    if (stage > 0) {   // the stage inputs and outputs of run_stage
+        double* a = g->us;
+        double* b = g->us + g->total;
+        const double* ins[4] = {u, a, b, a};
+        double* outs[4] = {a, b, a, u};
+        in_s = ins[stage - 1];
+        out_s = outs[stage - 1];
+    }
+    double* acc = (stage >= 1 && stage <= 3) ? g->acc : nullptr;
+    return launch_patch(A.view(nv), B.view(nv), in_s + A.off, I.kraw, I.kraw + n, out_s + A.off,
+                        acc ? acc + A.off : nullptr, out_s + B.off, acc ? acc + B.off : nullptr, dt, stage, st);
+}
+
+// One filtered RK4 step of every shell (Sec. 2.5), then the filter.  Runs go
+// one after the other; with nested shells every stage of all runs comes
+// before the next stage, with the interfaces coupled after each stage.
+static hipError_t step_launches(sg_grid* g, double* u, const double* dt, hipStream_t st, bool fork) {
+    hipError_t e;
+    const std::vector<Run> runs = make_runs(g, dt);
+    for (const Run& R : runs)
+        if (!run_fits(g, R)) return hipErrorInvalidValue;
+    const bool mixed = g->opt.precision != SG_PREC_FP64;
+    auto filt = [&](const Run& R) -> hipError_t {
+        if (g->opt.filter_kind == SG_FILTER_NONE) return hipSuccess;
+        double* u0 = u + g->sh[R.first].off;
+        return mixed ? filter_run_split(g, R, u0, st) : filter_run(g, R, u0, st);
+    };
+    if (g->ifaces.empty()) {
+        for (const Run& R : runs) {
+            for (int stage = 1; stage <= 4; ++stage)
+                if ((e = run_stage(g, R, u, dt, stage, st, fork)) != hipSuccess) return e;
+            if ((e = filt(R)) != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    for (int stage = 1; stage <= 4; ++stage) {
+        for (const Run& R : runs)
+            if ((e = run_stage(g, R, u, dt, stage, st, fork)) != hipSuccess) return e;
+        for (const Interface& I : g->ifaces)
+            if ((e = patch_interface(g, I, u, nullptr, dt[I.a], stage, st)) != hipSuccess) return e;
+    }
+    for (const Run& R : runs)
+        if ((e = filt(R)) != hipSuccess) return e;
     return hipSuccess;
 }
 
@@ -915,6 +993,8 @@ sg_status rk_step(sg_grid* g, double* u, const double* dt, int n_steps, sg_strea
         dts[s] = dt ? dt[s] : g->sh[s].dt;
         if (!(dts[s] > 0.0) || !std::isfinite(dts[s])) return fail(SG_EINVAL, "dt must be finite and positive");
     }
+    for (const Interface& I : g->ifaces)
+        if (dts[I.a] != dts[I.a + 1]) return fail(SG_EINVAL, "nested shells coupled at a sphere need one time step");
     // mixed precision: the split filter's reference u_ref is the state at the
     // start of this call, refreshed every kRefSteps steps (F(u_ref) in FP64),
     // so the FP32 part always rounds relative to the change of the state over

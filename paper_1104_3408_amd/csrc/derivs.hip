@@ -180,6 +180,134 @@ __device__ __forceinline__ void dtheta_tile(long long tile, const double* __rest
     }
 }
 
+// d_theta in FP64 on whole meridian plane pairs: workgroup `tile` = (f,
+// j), j < N_phi / 2, stages the planes phi_j and phi_j + pi of field f
+// (N_theta N_r contiguous values each, so every load and store covers whole
+// cache lines; the column tile above cuts the radial runs of N_r values at
+// arbitrary points) and forms d_theta of both planes for all N_r columns,
+// lane = k.  Arithmetic as dtheta_tile: S - mean and A, the equator pairs,
+// the operator of the equator-parity form.  LDS: 2 N_theta N_r doubles.
+template <int R>
+__device__ __forceinline__ void dtheta_plane_tile(long long tile, const double* __restrict__ in,
+                                                  double* __restrict__ out, const double* __restrict__ Hsb,
+                                                  int n_r, int n_th, int n_ph, double* __restrict__ sm) {
+    const int half = n_ph / 2;
+    const long long plane = (long long)n_th * n_r;
+    const long long f = tile / half;
+    const int jp = (int)(tile - f * half);
+    const double* src0 = in + (f * n_ph + jp) * plane;
+    const double* src1 = src0 + half * plane;
+    const int np_ = n_th * n_r;
+    const int nt = blockDim.x;
+    const int tid = threadIdx.x;
+    constexpr int U = 4;   // loads in flight per plane and thread
+    for (int base = 0; base < np_; base += U * nt) {
+        double a[U], b[U];
+#pragma unroll
+        for (int t = 0; t < U; ++t) {
+            const int e = base + tid + t * nt;
+            const int ec = e < np_ ? e : np_ - 1;   // in-bounds address for every thread
+            a[t] = src0[ec];
+            b[t] = src1[ec];
+        }
+#pragma unroll
+        for (int t = 0; t < U; ++t) {
+            const int e = base + tid + t * nt;
+            if (e < np_) {
+                sm[e] = a[t];
+                sm[np_ + e] = b[t];
+            }
+        }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int w = wave_id();
+    const int nw = nt >> 6;
+    double* sS = sm;          // rows i, column k at i n_r + k: S - mean, then equator pairs
+    double* sA = sm + np_;    // A, then equator pairs
+    double* spart = sm + 2 * np_;   // [nw][n_r] partial sums of S
+    // S = P0 + P1 and A = P0 - P1 in place; partial sums of S per column
+    for (int k0 = 0; k0 < n_r; k0 += 64) {
+        const int k = k0 + lane;
+        double part = 0.0;
+        if (k < n_r)
+            for (int i = w; i < n_th; i += nw) {
+                const double p0 = sS[i * n_r + k], p1 = sA[i * n_r + k];
+                sS[i * n_r + k] = p0 + p1;
+                sA[i * n_r + k] = p0 - p1;
+                part += p0 + p1;
+            }
+        if (k < n_r) spart[w * n_r + k] = part;
+    }
+    __syncthreads();
+    for (int k0 = 0; k0 < n_r; k0 += 64) {
+        const int k = k0 + lane;
+        if (k >= n_r) continue;
+        double mc = 0.0;
+        for (int v = 0; v < nw; ++v) mc += spart[v * n_r + k];
+        mc /= n_th;
+        for (int i = w; i < n_th / 2; i += nw) {   // S - mean, then the equator pairs of S and A
+            const int im = n_th - 1 - i;
+            const double s0 = sS[i * n_r + k] - mc, s1 = sS[im * n_r + k] - mc;
+            const double a0 = sA[i * n_r + k], a1 = sA[im * n_r + k];
+            sS[i * n_r + k] = s0 + s1;
+            sS[im * n_r + k] = s0 - s1;
+            sA[i * n_r + k] = a0 + a1;
+            sA[im * n_r + k] = a0 - a1;
+        }
+        if ((n_th & 1) && w == (n_th / 2) % nw) sS[(n_th / 2) * n_r + k] -= mc;   // middle row of an odd N_theta
+    }
+    __syncthreads();
+    const int hh = (n_th + 1) / 2;
+    const double* Ww = Hsb + (long long)w * hh * 4 * R;
+    double* o0 = out + (f * n_ph + jp) * plane;
+    double* o1 = o0 + half * plane;
+    for (int k0 = 0; k0 < n_r; k0 += 64) {
+        const int k = k0 + lane;
+        const int kc = k < n_r ? k : n_r - 1;
+        double qs[R], ps[R], qa[R], pa[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) qs[r] = ps[r] = qa[r] = pa[r] = 0.0;
+        #pragma unroll 2
+        for (int ip = 0; ip < hh; ++ip) {
+            const int im = n_th - 1 - ip;
+            const double sp = sS[ip * n_r + kc], smm = sS[im * n_r + kc];
+            const double ap = sA[ip * n_r + kc], am = sA[im * n_r + kc];
+            const double* wr = Ww + ip * 4 * R;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                qs[r] = fma(wr[r], sp, qs[r]);
+                ps[r] = fma(wr[R + r], smm, ps[r]);
+                qa[r] = fma(wr[2 * R + r], ap, qa[r]);
+                pa[r] = fma(wr[3 * R + r], am, pa[r]);
+            }
+        }
+        if (k >= n_r) continue;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = w * R + r;
+            if (i < hh) {
+                const double hs = qs[r] + ps[r], ha = qa[r] + pa[r];
+                o0[i * n_r + k] = 0.5 * (hs + ha);
+                o1[i * n_r + k] = 0.5 * (hs - ha);
+                const int im = n_th - 1 - i;
+                if (im != i) {
+                    const double hs2 = ps[r] - qs[r], ha2 = pa[r] - qa[r];
+                    o0[im * n_r + k] = 0.5 * (hs2 + ha2);
+                    o1[im * n_r + k] = 0.5 * (hs2 - ha2);
+                }
+            }
+        }
+    }
+}
+
+template <int R>
+__global__ __launch_bounds__(1024) void k_dtheta_plane(const double* __restrict__ in, double* __restrict__ out,
+                                                      const double* __restrict__ Hsb, int n_r, int n_th, int n_ph) {
+    extern __shared__ double smd[];
+    dtheta_plane_tile<R>(blockIdx.x, in, out, Hsb, n_r, n_th, n_ph, smd);
+}
+
 template <int R, typename T, typename O>
 __global__ __launch_bounds__(1024) void k_dtheta(const double* __restrict__ in, O* __restrict__ out,
                                                 const T* __restrict__ Hsb,
@@ -398,7 +526,7 @@ struct D3Dims {
     long long n_lines, n_cols_th, ncol_ph;
     unsigned b_dr, b_th, bx_ph;
     int nf;
-    int R_dr, R_th, R_ph, ph_par;
+    int R_dr, R_th, R_ph, ph_par, th_plane;
     int n_r, n_th, n_ph;
 };
 
@@ -433,6 +561,16 @@ __global__ __launch_bounds__(1024) void k_derivs3(const double* __restrict__ in,
         return;
     }
     if (is_th) {
+        if constexpr (sizeof(T) == sizeof(double)) {
+            if (a.th_plane) {
+                switch (a.R_th) {
+#define X(R) case R: dtheta_plane_tile<R>(t_th, in, out_th, Hsb, a.n_r, a.n_th, a.n_ph, smd); break;
+                    X(1) X(2) X(3) X(4)
+#undef X
+                }
+                return;
+            }
+        }
         switch (a.R_th) {
 #define X(R) case R: dtheta_tile<R, T, O>(t_th, in, out_th, Hsb, a.n_r, a.n_th, a.n_ph, a.n_cols_th, smd); break;
             X(1) X(2) X(3) X(4)
@@ -522,6 +660,19 @@ hipError_t launch_dr(const KShell& s, const double* in, double* out, int n_field
 template <typename T, typename O>
 static hipError_t dtheta_t(const KShell& s, const double* in, O* out, const T* Hsb, int n_fields,
                            hipStream_t st) {
+    if constexpr (sizeof(T) == sizeof(double)) {
+        if (s.th_plane) {   // whole meridian plane pairs per workgroup
+            const unsigned blocks = (unsigned)((long long)n_fields * (s.n_ph / 2));
+            const size_t shm = sizeof(double) * (2 * size_t(s.n_th) * s.n_r + size_t(s.Hth_nw) * s.n_r);
+            switch (s.Hth_R) {
+#define X(R) case R: hipLaunchKernelGGL((k_dtheta_plane<R>), dim3(blocks), dim3(64u * s.Hth_nw), shm, st, in, out, Hsb, s.n_r, s.n_th, s.n_ph); break;
+                X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8)
+#undef X
+                default: return hipErrorInvalidValue;
+            }
+            return hipGetLastError();
+        }
+    }
     const long long n_cols = (long long)n_fields * (s.n_ph / 2) * s.n_r;
     const unsigned blocks = (unsigned)((n_cols + 63) / 64);
     if (s.n_th > s.Hth_nw * kThMaxPerThread) return hipErrorInvalidValue;
@@ -618,7 +769,8 @@ static hipError_t derivs3_t(const KShell& s, const AxisOp& dph, const T* Wph, co
     a.n_cols_th = (long long)n_fields * (s.n_ph / 2) * s.n_r;
     a.ncol_ph = (long long)s.n_th * s.n_r;
     a.b_dr = (unsigned)((a.n_lines + 63) / 64);
-    a.b_th = (unsigned)((a.n_cols_th + 63) / 64);
+    a.th_plane = sizeof(T) == sizeof(double) && s.th_plane;
+    a.b_th = a.th_plane ? (unsigned)(n_fields * (s.n_ph / 2)) : (unsigned)((a.n_cols_th + 63) / 64);
     a.bx_ph = (unsigned)((a.ncol_ph + 63) / 64);
     a.nf = n_fields;
     a.R_dr = s.Dr_R;
@@ -630,7 +782,8 @@ static hipError_t derivs3_t(const KShell& s, const AxisOp& dph, const T* Wph, co
     a.n_ph = s.n_ph;
     const size_t part = size_t(nw) * 64 * sizeof(double);
     size_t shm = sizeof(double) * size_t(s.n_r) * kDrStride;
-    shm = std::max(shm, sizeof(T) * 2 * size_t(s.n_th) * 64 + part);
+    shm = std::max(shm, a.th_plane ? sizeof(double) * (2 * size_t(s.n_th) * s.n_r + size_t(nw) * s.n_r)
+                                   : sizeof(T) * 2 * size_t(s.n_th) * 64 + part);
     shm = std::max(shm, sizeof(T) * size_t(s.n_ph) * 64 + part);
     const unsigned long long blocks = (unsigned long long)a.b_dr + a.b_th + (unsigned long long)a.bx_ph * n_fields;
     if (blocks >= (1ull << 31)) return hipErrorNotSupported;

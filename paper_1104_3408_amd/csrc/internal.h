@@ -19,12 +19,19 @@ struct KShell {
     const double* Hsb;        // theta operator in the equator-parity form of dtheta_tile, wave-blocked
     int Dr_R, Hth_R;          // rows per wave of the blocked d_r / d_theta operators
     int Dr_nw, Hth_nw;        // waves per workgroup of k_dr / k_dtheta
+    int th_plane;             // FP64 d_theta on whole meridian plane pairs (k_dtheta_plane)
     const float* Hsb_f;       // FP32 copy for the mixed-precision path
     const double* rk;         // radii
     const double* sth; const double* cth;   // sin, cos theta_i
     const double* sph; const double* cph;   // sin, cos phi_j
     const double* H;          // static gauge H_a, [4][npts]
     const double* dH;         // Cartesian d_i H_b, [3][4][npts]
+    // nested shells (SG_NESTED): the right-hand side at the outer (inner)
+    // sphere, before any boundary treatment, is also stored here,
+    // [n_v][N_theta N_phi]; an outer sphere with kraw_out gets no boundary
+    // operator (the interface kernel couples it)
+    double* kraw_out;
+    double* kraw_in;
 };
 
 // One group of filter columns: a real column (im < 0) or the real and
@@ -67,6 +74,7 @@ struct AxisOp {
 // workgroup of the derivative kernels (4 kMaxWaves rows cover n <= 320).
 constexpr int kMaxRows = 20;
 constexpr int kMaxWaves = 16, kMinWaves = 8;
+constexpr size_t kMaxLdsBytes = 160 * 1024;   // LDS of one workgroup on gfx950
 // Tile shapes of one shell size: target output rows per wave of the d_r,
 // d_theta, d_phi, phi-analysis and phi-synthesis contractions (fewer rows
 // means more waves on one staged tile, see blocked_shape) and waves per
@@ -77,6 +85,7 @@ constexpr int kMaxWaves = 16, kMinWaves = 8;
 struct Tune {
     int dr_rows = 9, th_rows = 4, dph_rows = 8, ana_rows = 8, syn_rows = 8, filt_waves = 8;
     int dph_par = -1;   // d_phi form: 0 circulant window, 1 parity; -1: parity in FP32 modes only
+    int th_plane = 0;   // FP64 d_theta tile: 0 64 columns, 1 a meridian plane pair
 };
 // The table entry for this shell size, or the defaults; *source names where
 // it came from (the table's path, or "defaults").
@@ -99,6 +108,7 @@ struct ShellHost {
     double *Drb = nullptr, *Hsb = nullptr;
     float *Hsb_f = nullptr;
     int Dr_R = 0, Hth_R = 0, Dr_nw = 0, Hth_nw = 0;
+    int th_plane = 0;
     AxisOp dph, ana, syn;                    // d_phi, Fourier analysis, Fourier synthesis
     Bf3Op bf_dph, bf_hs, bf_ha;              // split d_phi, H_L + H_R, H_L - H_R (BF16X3 only)
     Bf3Op bf_ana, bf_syn;                    // split phi analysis / synthesis of the filter (BF16X3 only)
@@ -109,6 +119,7 @@ struct ShellHost {
     int F_R = 0, F_nw = 0;                   // theta rows per wave and waves per workgroup of Fb
     Tune tune;                               // tile shapes of this shell size
     double *H = nullptr, *dH = nullptr;      // static gauge
+    double *kraw_out = nullptr, *kraw_in = nullptr;   // interface right-hand sides (SG_NESTED)
     bool owns_ops = true;                    // false: operators belong to an earlier identical shell
     std::vector<double> r_host, th_host, ph_host;
     KShell view(int n_v) const;
@@ -118,6 +129,12 @@ struct ShellHost {
 // Consecutive shells with identical grids: one launch per kernel covers them.
 struct Run {
     int first = 0, count = 0;
+};
+
+// A sphere shared by shell a (its outer sphere) and shell a + 1 (its inner).
+struct Interface {
+    int a = 0;
+    double* kraw = nullptr;   // [2][n_v][N_theta N_phi]: raw rhs of shell a, then of shell a + 1
 };
 
 // Steps per replay of the longer step graph: consecutive replays of one graph
@@ -177,6 +194,7 @@ struct sg_grid {
     hipEvent_t fork_ev[3] = {nullptr, nullptr, nullptr};
     sg::StepGraph sgraph;            // one filtered step
     sg::StepGraph sgraph_k;          // kGraphSteps filtered steps
+    std::vector<sg::Interface> ifaces;   // nested-shell interfaces (SG_NESTED)
 };
 
 namespace sg {
@@ -244,6 +262,15 @@ hipError_t launch_ftheta(const KShell& s, int count, const double* spec, double*
 hipError_t launch_initial(const KShell& s, const double* g10, const double* dg, double* u,
                           double* H, hipStream_t st);
 hipError_t launch_finite_check(const double* u, size_t n, int* flag, hipStream_t st);
+// Interface of nested shells a (inside) and b (outside): the common
+// right-hand side of the two copies of the shared sphere from the raw ones
+// (ka, kb: [n_v][N_theta N_phi]), ua the stage input state of shell a; the
+// copies' stage outputs (and RK accumulators, stages 1-3) are corrected by
+// the difference to the raw right-hand side with the stage's coefficients
+// (stage 0: out is the right-hand side itself).
+hipError_t launch_patch(const KShell& a, const KShell& b, const double* ua, const double* ka, const double* kb,
+                        double* out_a, double* acc_a, double* out_b, double* acc_b, double dt, int stage,
+                        hipStream_t st);
 // dg: Cartesian derivatives of the ten g_ab, block x at dg + x * dblk;
 // part: ceil(npts/256) * 4 doubles of workspace; norms: 4 doubles.
 hipError_t launch_constraints(const KShell& s, const double* u, const double* dg, long long dblk, double* part,

@@ -298,8 +298,9 @@ __global__ __launch_bounds__(kWaves * 64, 2) void k_rhs(KShell s, const double* 
                     + al * dg[x] - al * dP[x] + bu[0] * dF[x][0] + bu[1] * dF[x][1] + bu[2] * dF[x][2];
         // eq. gdot
         double rg = -al * Pab + bF;
-        // outer boundary: freeze incoming characteristic fields (App. A.3)
-        if (k == s.n_r - 1) {
+        // outer boundary: freeze incoming characteristic fields (App. A.3); an
+        // interface sphere of nested shells is coupled by k_patch instead
+        if (k == s.n_r - 1 && !s.kraw_out) {
             const double xh[3] = {st * cp, st * sp, ct};
             double su_[3];
 #pragma unroll
@@ -322,9 +323,12 @@ __global__ __launch_bounds__(kWaves * 64, 2) void k_rhs(KShell s, const double* 
         }
         if constexpr (decltype(NC)::value >= 0) load_pair(decltype(NC)::value, dn);
         if (ok) {
+            const long long nang = np / s.n_r, ang = p / s.n_r;   // angular point of this lane
+            double* kraw = (k == s.n_r - 1) ? s.kraw_out : (k == 0 ? s.kraw_in : nullptr);
             auto emit = [&](int m, double kv) {
                 const int mu = q + 10 * m;
                 const long long o = (long long)mu * np + p;
+                if (kraw) kraw[mu * nang + ang] = kv;
                 if (stage == 0) {
                     out[o] = kv;
                 } else if (stage == 1) {        // k1 at u: acc = u + dt/6 k1, us = u + dt/2 k1
@@ -350,6 +354,7 @@ __global__ __launch_bounds__(kWaves * 64, 2) void k_rhs(KShell s, const double* 
                 for (int c = 0; c < 8; ++c) {
                     const long long o = (long long)(50 + c) * np + p;
                     const double kv = c < 4 ? sdH[0][c][lane] : 0.0;
+                    if (kraw) kraw[(50 + c) * nang + ang] = kv;
                     const double u0 = su[50 + c][lane];
                     if (stage == 0) {
                         out[o] = kv;
@@ -571,6 +576,110 @@ __global__ __launch_bounds__(256) void k_constraint_norms(const double* __restri
     }
 }
 
+// Interface of nested shells a (inside) and b (outside) sharing a sphere
+// (the outlook of Sec. 1 and Sec. 5; the interface condition is this
+// library's reading): both copies of the sphere get one right-hand side.  For
+// every symmetric pair the raw right-hand sides are taken apart into the
+// characteristic fields of App. A.2 (eq. characteristics) with s_i the unit
+// normal from a into b: u^0 = g (speed 0), u^1+- = -g + Pi +- s^k Phi_k
+// (speeds +-alpha - b), u^2_i = P^k_i Phi_k (speed -b), b = s_k beta^k; each
+// is taken from the side it travels from (speed > 0: a, < 0: b, 0: the mean)
+// and transformed back:
+//   d g = u^0,  d Pi = u^0 + (u^1+ + u^1-)/2,  d Phi_i = s_i (u^1+ - u^1-)/2 + u^2_i.
+// The gauge fields of the 58-field form (no spatial derivatives) take the
+// mean.  The copies' stage outputs were formed from the raw right-hand
+// sides; they are corrected here by the stage coefficients times the
+// difference (stage 0: the output is the right-hand side).
+__global__ __launch_bounds__(256) void k_patch(KShell sa, KShell sb, const double* __restrict__ ua,
+                                               const double* __restrict__ ka, const double* __restrict__ kb,
+                                               double* __restrict__ out_a, double* __restrict__ acc_a,
+                                               double* __restrict__ out_b, double* __restrict__ acc_b, double dt,
+                                               int stage) {
+    const long long nang = (long long)sa.n_th * sa.n_ph;
+    const long long ang = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (ang >= nang) return;
+    const int i = (int)(ang % sa.n_th), j = (int)(ang / sa.n_th);
+    const long long pa = (long long)(sa.n_r - 1) + sa.n_r * ang, pb = (long long)sb.n_r * ang;
+    const long long npa = sa.npts, npb = sb.npts;
+    // 3+1 quantities of the state at the sphere (the copies are equal)
+    double g[10];
+#pragma unroll
+    for (int q = 0; q < 10; ++q) g[q] = ua[q * npa + pa];
+    const double gxx = g[4], gxy = g[5], gxz = g[6], gyy = g[7], gyz = g[8], gzz = g[9];
+    const double cxx = gyy * gzz - gyz * gyz, cxy = gxz * gyz - gxy * gzz, cxz = gxy * gyz - gxz * gyy;
+    const double cyy = gxx * gzz - gxz * gxz, cyz = gxy * gxz - gxx * gyz, czz = gxx * gyy - gxy * gxy;
+    const double idet = 1.0 / (gxx * cxx + gxy * cxy + gxz * cxz);
+    const double gi[3][3] = {{cxx * idet, cxy * idet, cxz * idet},
+                             {cxy * idet, cyy * idet, cyz * idet},
+                             {cxz * idet, cyz * idet, czz * idet}};
+    const double bl[3] = {g[1], g[2], g[3]};
+    double bu[3];
+#pragma unroll
+    for (int x = 0; x < 3; ++x) bu[x] = gi[x][0] * bl[0] + gi[x][1] * bl[1] + gi[x][2] * bl[2];
+    const double al = sqrt(bu[0] * bl[0] + bu[1] * bl[1] + bu[2] * bl[2] - g[0]);
+    const double st = sa.sth[i], ct = sa.cth[i], sp = sa.sph[j], cp = sa.cph[j];
+    const double xh[3] = {st * cp, st * sp, ct};
+    double su_[3];
+#pragma unroll
+    for (int x = 0; x < 3; ++x) su_[x] = gi[x][0] * xh[0] + gi[x][1] * xh[1] + gi[x][2] * xh[2];
+    const double inorm = 1.0 / sqrt(su_[0] * xh[0] + su_[1] * xh[1] + su_[2] * xh[2]);
+    double sl[3], sup[3];
+#pragma unroll
+    for (int x = 0; x < 3; ++x) {
+        sl[x] = xh[x] * inorm;
+        sup[x] = su_[x] * inorm;
+    }
+    const double b = sl[0] * bu[0] + sl[1] * bu[1] + sl[2] * bu[2];
+    // 0: from a, 1: from b, 0.5: mean (speed 0)
+    auto pick = [](double v) { return v > 0.0 ? 0.0 : (v < 0.0 ? 1.0 : 0.5); };
+    const double wp = pick(al - b), wm = pick(-al - b), wt = pick(-b);
+    double co = 1.0, cacc = 0.0;   // stage coefficients of out and acc (RK4, Sec. 2.5)
+    if (stage == 1) { co = 0.5 * dt; cacc = dt / 6.0; }
+    else if (stage == 2) { co = 0.5 * dt; cacc = dt / 3.0; }
+    else if (stage == 3) { co = dt; cacc = dt / 3.0; }
+    else if (stage == 4) { co = dt / 6.0; }
+    auto put = [&](int mu, double kp) {
+        const double da = kp - ka[mu * nang + ang], db = kp - kb[mu * nang + ang];
+        const long long oa = mu * npa + pa, ob = mu * npb + pb;
+        if (stage == 0) {
+            out_a[oa] = kp;
+            out_b[ob] = kp;
+            return;
+        }
+        out_a[oa] += co * da;
+        out_b[ob] += co * db;
+        if (cacc != 0.0) {
+            acc_a[oa] += cacc * da;
+            acc_b[ob] += cacc * db;
+        }
+    };
+    for (int q = 0; q < 10; ++q) {
+        double cA[6], cB[6];   // u^0, u^1+, u^1-, u^2_x, u^2_y, u^2_z
+        const double* ks[2] = {ka, kb};
+        double* cs[2] = {cA, cB};
+        for (int side = 0; side < 2; ++side) {
+            const double* kk = ks[side];
+            const double dg = kk[q * nang + ang], dP = kk[(10 + q) * nang + ang];
+            const double dF[3] = {kk[(20 + q) * nang + ang], kk[(30 + q) * nang + ang], kk[(40 + q) * nang + ang]};
+            const double sF = sup[0] * dF[0] + sup[1] * dF[1] + sup[2] * dF[2];
+            double* c = cs[side];
+            c[0] = dg;
+            c[1] = -dg + dP + sF;
+            c[2] = -dg + dP - sF;
+#pragma unroll
+            for (int x = 0; x < 3; ++x) c[3 + x] = dF[x] - sl[x] * sF;
+        }
+        const double u0 = 0.5 * (cA[0] + cB[0]);
+        const double up = (1.0 - wp) * cA[1] + wp * cB[1];
+        const double um = (1.0 - wm) * cA[2] + wm * cB[2];
+        put(q, u0);
+        put(10 + q, u0 + 0.5 * (up + um));
+#pragma unroll
+        for (int x = 0; x < 3; ++x) put(20 + 10 * x + q, sl[x] * 0.5 * (up - um) + (1.0 - wt) * cA[3 + x] + wt * cB[3 + x]);
+    }
+    for (int mu = 50; mu < sa.n_v; ++mu) put(mu, 0.5 * (ka[mu * nang + ang] + kb[mu * nang + ang]));
+}
+
 __global__ __launch_bounds__(256) void k_finite(const double* __restrict__ u, size_t n, int* flag) {
     int bad = 0;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
@@ -626,6 +735,15 @@ hipError_t launch_constraints(const KShell& s, const double* u, const double* dg
 hipError_t launch_constraint_norms(const KShell& s, const double* part, double* norms, hipStream_t st) {
     const unsigned blocks = (unsigned)((s.npts + 255) / 256);
     hipLaunchKernelGGL(k_constraint_norms, dim3(1), dim3(256), 0, st, part, (int)blocks, (long long)s.npts, norms);
+    return hipGetLastError();
+}
+
+hipError_t launch_patch(const KShell& a, const KShell& b, const double* ua, const double* ka, const double* kb,
+                        double* out_a, double* acc_a, double* out_b, double* acc_b, double dt, int stage,
+                        hipStream_t st) {
+    const long long nang = (long long)a.n_th * a.n_ph;
+    hipLaunchKernelGGL(k_patch, dim3((unsigned)((nang + 255) / 256)), dim3(256), 0, st, a, b, ua, ka, kb, out_a,
+                       acc_a, out_b, acc_b, dt, stage);
     return hipGetLastError();
 }
 

@@ -18,6 +18,7 @@ SG_PREC_FP64, SG_PREC_FP32, SG_PREC_BF16X3 = 0, 1, 2
 SG_COORD, SG_CART = 0, 1
 SG_CHECK_FINITE = 1
 SG_NO_GRAPH = 2
+SG_NESTED = 4
 
 KERNEL_CLASSES = ["d_r", "d_theta", "d_phi", "rhs_stage", "filter_decompose", "filter_phi_analysis",
                   "filter_theta", "filter_phi_synthesis", "filter_recompose"]

