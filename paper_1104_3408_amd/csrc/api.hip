@@ -185,10 +185,10 @@ size_t layout_offset(const sg_grid* g, int shell, int nfield) {
 
 // The three derivative contractions are independent.  They run as one
 // launch (launch_derivs3) whenever their blocked shapes agree on the waves
-// per workgroup and the timing mode is off; otherwise, with fork (graph
-// capture only), d_theta and d_phi run on the two side streams beside d_r
-// and the stream waits for both, so the captured graph holds three parallel
-// nodes.
+// per workgroup, the tuning table does not ask for separate launches (fuse
+// 0) and the timing mode is off; otherwise, with fork (graph capture only),
+// d_theta and d_phi run on the two side streams beside d_r and the stream
+// waits for both, so the captured graph holds three parallel nodes.
 static hipError_t fork_begin(sg_grid* g, hipStream_t st) {
     hipError_t e;
     if ((e = hipEventRecord(g->fork_ev[0], st)) != hipSuccess) return e;
@@ -239,7 +239,7 @@ hipError_t derivs_shell(sg_grid* g, int s, const double* in, double* out, int nf
     const KShell v = S.view(nfield);
     const long long cnt = (long long)S.npts * nfield;
     hipError_t e;
-    if (!g->tm.on) {   // one launch for the three (the timing mode keeps them apart, one class each)
+    if (!g->tm.on && S.tune.fuse) {   // one launch for the three (the timing mode keeps them apart)
         e = launch_derivs3(v, S.dph, in, out, nfield, st);
         if (e == hipSuccess) return cart ? launch_chain(v, out, nfield, st) : hipSuccess;
         if (e != hipErrorNotSupported) return e;
@@ -264,7 +264,7 @@ hipError_t derivs_shell_mixed(sg_grid* g, int s, const double* in, double* dr, f
     hipError_t e;
     auto l_dr = [&](hipStream_t q) { return launch_dr(v, in, dr, nfield, q); };
     if (g->opt.precision == SG_PREC_BF16X3) {   // angular contractions on the matrix cores
-        if (!g->tm.on) {
+        if (!g->tm.on && S.tune.fuse) {
             e = launch_derivs3_bf3(v, S.bf_dph, S.bf_hs, S.bf_ha, in, dr, dang, nfield, st);
             if (e != hipErrorNotSupported) return e;
         }
@@ -272,7 +272,7 @@ hipError_t derivs_shell_mixed(sg_grid* g, int s, const double* in, double* dr, f
             g, st, fork, l_dr, [&](hipStream_t q) { return launch_bf3_dtheta(v, S.bf_hs, S.bf_ha, in, dang, nfield, q); },
             [&](hipStream_t q) { return launch_bf3_dphi(v, S.bf_dph, in, dang + cnt, nfield, q); });
     }
-    if (!g->tm.on) {
+    if (!g->tm.on && S.tune.fuse) {
         e = launch_derivs3_mixed(v, S.dph, in, dr, dang, nfield, st);
         if (e != hipErrorNotSupported) return e;
     }

@@ -250,7 +250,8 @@ __global__ __launch_bounds__(256) void k_bf3_theta(const double* __restrict__ in
                                                    const __bf16* __restrict__ Ahi, const __bf16* __restrict__ Alo,
                                                    int n_r, int n_th, int n_ph, int K, int M, long long n_cols) {
     extern __shared__ double smd[];
-    bf3_theta_tile<4>(blockIdx.x, in, out, Shi, Slo, Ahi, Alo, n_r, n_th, n_ph, K, M, n_cols, smd);
+    bf3_theta_tile<4>(xcd_block(blockIdx.x, gridDim.x), in, out, Shi, Slo, Ahi, Alo, n_r, n_th, n_ph, K, M, n_cols,
+                      smd);
 }
 
 // Theta filter of the split filter's FP32 spectral columns on the matrix
@@ -275,9 +276,10 @@ __global__ __launch_bounds__(256) void k_ftheta_bf3(int n_r, int n_th, int m_kee
     __bf16* x1h = x0l + 64 * ldx;
     __bf16* x1l = x1h + 64 * ldx;
     float* res = reinterpret_cast<float*>(x1l + 64 * ldx);   // [2][n_th][64]
-    const int m = blockIdx.y;
-    const FiltSet fs = sets[blockIdx.z % n_sets];
-    const int shell = blockIdx.z / n_sets;
+    const Blk3 b = xcd_block3();   // (column tile, m, set x shell), tiles of one range on one XCD
+    const int m = b.y;
+    const FiltSet fs = sets[b.z % n_sets];
+    const int shell = b.z / n_sets;
     const long long per_m = (long long)n_th * n_r;
     const long long col = (long long)(2 * m_keep + 1) * per_m;   // one storage column
     {
@@ -285,7 +287,7 @@ __global__ __launch_bounds__(256) void k_ftheta_bf3(int n_r, int n_th, int m_kee
         spec += so;
         spec2 += so;
     }
-    const long long c0 = (long long)blockIdx.x * 64;
+    const long long c0 = (long long)b.x * 64;
     if (c0 >= (long long)fs.count * n_r) return;
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);

@@ -313,7 +313,7 @@ __global__ __launch_bounds__(1024) void k_dtheta(const double* __restrict__ in, 
                                                 const T* __restrict__ Hsb,
                                                 int n_r, int n_th, int n_ph, long long n_cols) {
     extern __shared__ double smd[];
-    dtheta_tile<R, T, O>(blockIdx.x, in, out, Hsb, n_r, n_th, n_ph, n_cols, smd);
+    dtheta_tile<R, T, O>(xcd_block(blockIdx.x, gridDim.x), in, out, Hsb, n_r, n_th, n_ph, n_cols, smd);
 }
 
 // out[f][q][c] = sum_r W[q][r] (in[f][r][c] - m_c),  m_c = mean of column c
@@ -546,7 +546,7 @@ __global__ __launch_bounds__(1024) void k_derivs3(const double* __restrict__ in,
     // block b is the D(b)-th d_r tile if D(b + 1) > D(b), D(b) = floor(b b_dr / B);
     // otherwise the same rule splits the rest between d_theta and d_phi
     const unsigned long long B = (unsigned long long)a.b_dr + a.b_th + (unsigned long long)a.bx_ph * a.nf;
-    const unsigned long long bb = blockIdx.x;
+    const unsigned long long bb = blockIdx.x;   // (the XCD renumbering of k_dtheta measured slower here)
     const unsigned long long d0 = bb * a.b_dr / B, d1 = (bb + 1) * a.b_dr / B;
     const unsigned long long o = bb - d0, n_o = B - a.b_dr;   // index among the other tiles
     const unsigned long long t0 = n_o ? o * a.b_th / n_o : 0, t1 = n_o ? (o + 1) * a.b_th / n_o : 0;

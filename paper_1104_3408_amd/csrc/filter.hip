@@ -355,9 +355,10 @@ __global__ __launch_bounds__(64 * NW) void k_ftheta(int n_r, int n_th, int m_kee
                                                 const FiltSet* __restrict__ sets, int n_sets) {
     extern __shared__ double smd[];   // v0, v1: [n_th][64] in T
     T* sm = reinterpret_cast<T*>(smd);
-    const int m = blockIdx.y;
-    const FiltSet fs = sets[blockIdx.z % n_sets];
-    const int shell = blockIdx.z / n_sets;
+    const Blk3 b = xcd_block3();   // (column tile, m, set x shell), tiles of one range on one XCD
+    const int m = b.y;
+    const FiltSet fs = sets[b.z % n_sets];
+    const int shell = b.z / n_sets;
     const long long per_m = (long long)n_th * n_r;
     const long long col = (long long)(2 * m_keep + 1) * per_m;   // one storage column
     {
@@ -365,7 +366,7 @@ __global__ __launch_bounds__(64 * NW) void k_ftheta(int n_r, int n_th, int m_kee
         spec += so;
         spec2 += so;
     }
-    const long long c0 = (long long)blockIdx.x * 64;
+    const long long c0 = (long long)b.x * 64;
     if (c0 >= (long long)fs.count * n_r) return;
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);

@@ -75,6 +75,29 @@ struct AxisOp {
 constexpr int kMaxRows = 20;
 constexpr int kMaxWaves = 16, kMinWaves = 8;
 constexpr size_t kMaxLdsBytes = 160 * 1024;   // LDS of one workgroup on gfx950
+
+// The 8 XCDs of the chip take the workgroups of a launch round-robin by linear
+// id, each with its own L2.  xcd_block(b, n) renumbers the n workgroups so
+// that XCD x runs one contiguous range of tiles: neighbouring tiles whose
+// HBM rows share cache lines at their edges then meet in the same L2 instead
+// of fetching the shared lines once per XCD.  A bijection of [0, n).
+constexpr unsigned kXcds = 8;
+__device__ __forceinline__ unsigned long long xcd_block(unsigned long long b, unsigned long long n) {
+    const unsigned long long x = b % kXcds, per = n / kXcds, rem = n % kXcds;
+    return x * per + (x < rem ? x : rem) + b / kXcds;
+}
+
+// (x, y, z) of this workgroup in a 3-d grid after xcd_block on its linear id.
+struct Blk3 {
+    unsigned x, y, z;
+};
+__device__ __forceinline__ Blk3 xcd_block3() {
+    const unsigned long long n = (unsigned long long)gridDim.x * gridDim.y * gridDim.z;
+    const unsigned long long L = xcd_block(
+        blockIdx.x + (unsigned long long)gridDim.x * (blockIdx.y + (unsigned long long)gridDim.y * blockIdx.z), n);
+    const unsigned long long t = L / gridDim.x;
+    return Blk3{(unsigned)(L % gridDim.x), (unsigned)(t % gridDim.y), (unsigned)(t / gridDim.y)};
+}
 // Tile shapes of one shell size: target output rows per wave of the d_r,
 // d_theta, d_phi, phi-analysis and phi-synthesis contractions (fewer rows
 // means more waves on one staged tile, see blocked_shape) and waves per
@@ -86,6 +109,7 @@ struct Tune {
     int dr_rows = 9, th_rows = 4, dph_rows = 8, ana_rows = 8, syn_rows = 8, filt_waves = 8;
     int dph_par = -1;   // d_phi form: 0 circulant window, 1 parity; -1: parity in FP32 modes only
     int th_plane = 0;   // FP64 d_theta tile: 0 64 columns, 1 a meridian plane pair
+    int fuse = 1;       // the three derivative contractions as one launch where the shapes allow
 };
 // The table entry for this shell size, or the defaults; *source names where
 // it came from (the table's path, or "defaults").

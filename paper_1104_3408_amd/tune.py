@@ -3,14 +3,17 @@
 For every shell size of the benchmark workloads and every precision mode it
 times the candidate tile shapes of each contraction kernel class with HIP
 events (the library's timing mode: eager launches, one kernel class each) on
-a batch of identical shells as the workloads run them, keeps the fastest per
-class, then compares whole captured steps of the tuned shapes against the
-defaults (the three derivative contractions of a stage run as one launch only
-when their workgroups agree, which the per-class choice may undo) and keeps
-the faster.  The result is a text table, one line per (N_r, N_theta,
-n_fields, precision), read by shell_grid_create (see csrc/tuning.cpp):
+a batch of identical shells as the workloads run them and keeps the fastest
+per class.  Whole captured steps then decide what per-class timings cannot
+see: the three derivative contractions of a stage as one launch (which needs
+their workgroups to agree) or as three launches on forked streams, the d_theta
+tile inside them, and the tuned shapes against the defaults (--forms-only
+makes only this choice, on the shapes of an existing table).  The result is a
+text table, one line per (N_r, N_theta, n_fields, precision), read by
+shell_grid_create (see csrc/tuning.cpp):
 
   python -m paper_1104_3408_amd.tune [--out paper_1104_3408_amd/tuning.txt] [--classes 17,25,33,49,65]
+                                     [--precisions 0,1,2] [--merge] [--forms-only]
 
 Candidate values are target rows per wave (blocked_shape turns a target into
 rows per wave and 8, 12 or 16 waves per workgroup; targets giving the same
@@ -25,9 +28,9 @@ import tempfile
 import time
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-FIELDS = ["dr_rows", "th_rows", "dph_rows", "ana_rows", "syn_rows", "filt_waves", "dph_par", "th_plane"]
+FIELDS = ["dr_rows", "th_rows", "dph_rows", "ana_rows", "syn_rows", "filt_waves", "dph_par", "th_plane", "fuse"]
 DEFAULT = {"dr_rows": 9, "th_rows": 4, "dph_rows": 8, "ana_rows": 8, "syn_rows": 8, "filt_waves": 8, "dph_par": -1,
-           "th_plane": 0}
+           "th_plane": 0, "fuse": 1}
 # kernel class (KERNEL_CLASSES order of the binding) timed for each field
 FIELD_CLASS = {"dr_rows": "d_r", "th_rows": "d_theta", "dph_rows": "d_phi", "ana_rows": "filter_phi_analysis",
                "syn_rows": "filter_phi_synthesis", "filt_waves": "filter_theta", "dph_par": "d_phi",
@@ -142,7 +145,7 @@ def tune_class(key, table_path):
         return memo[k]
     report = {}
     # the d_phi form first: it decides what dph_rows counts
-    for field in ["dph_par"] + [f for f in FIELDS if f != "dph_par"]:
+    for field in ["dph_par"] + [f for f in FIELDS if f not in ("dph_par", "fuse")]:
         cls = FIELD_CLASS[field]
         if field == "filt_waves":
             cands = [4, 8, 16]
@@ -166,13 +169,31 @@ def tune_class(key, table_path):
         best[field] = v_best
         report[field] = {str(v): round(t, 4) for v, t in times.items()}
         log("%s %s: %s -> %s" % (key, field, report[field], v_best))
-    # whole captured steps: tuned shapes against the defaults
-    t_tuned = measure(key, best, table_path, steps=6, graph=True)
-    t_def = measure(key, DEFAULT, table_path, steps=6, graph=True)
-    log("%s graph step: tuned %.3f ms, defaults %.3f ms" % (key, t_tuned, t_def))
-    if t_def < t_tuned:
-        best = dict(DEFAULT)
-    return best, {"per_class_ms": report, "graph_ms_tuned": t_tuned, "graph_ms_defaults": t_def}
+    graph = choose_forms(key, best, table_path)
+    return graph["best"], {"per_class_ms": report, "graph_ms": graph["graph_ms"]}
+
+
+def choose_forms(key, tuned, table_path):
+    """Whole captured steps decide what the per-class timings cannot see:
+    the one-launch form of the three derivative contractions against three
+    launches on forked streams (fuse), the d_theta tile inside each, and the
+    tuned shapes against the defaults."""
+    prec = key[3]
+    cands = {"tuned": dict(tuned, fuse=1), "tuned, three launches": dict(tuned, fuse=0),
+             "defaults": dict(DEFAULT)}
+    if prec == 0:
+        flip = 1 - tuned["th_plane"]
+        cands["tuned, other theta tile"] = dict(tuned, fuse=1, th_plane=flip)
+        cands["tuned, three launches, other theta tile"] = dict(tuned, fuse=0, th_plane=flip)
+    graph_ms, seen = {}, {}
+    for name, t in cands.items():
+        k = tuple(t[f] for f in FIELDS)
+        if k not in seen:
+            seen[k] = measure(key, t, table_path, steps=6, graph=True)
+        graph_ms[name] = round(seen[k], 4)
+    name = min(graph_ms, key=graph_ms.get)
+    log("%s graph step ms: %s -> %s" % (key, graph_ms, name))
+    return {"best": cands[name], "graph_ms": graph_ms}
 
 
 def main():
@@ -181,6 +202,8 @@ def main():
     ap.add_argument("--classes", default="17,25,33,49,65")
     ap.add_argument("--precisions", default="0,1,2")
     ap.add_argument("--merge", action="store_true", help="keep the other entries of an existing table")
+    ap.add_argument("--forms-only", action="store_true",
+                    help="keep the tile shapes of the existing table and only choose the forms by step time")
     args = ap.parse_args()
     import json
     entries, details = {}, {}
@@ -193,7 +216,11 @@ def main():
             for c in [int(x) for x in args.classes.split(",")]:
                 n_r, n_th, n_v, _, _ = CLASSES[c]
                 key = (n_r, n_th, n_v, prec)
-                entries[key], details[str(key)] = tune_class(key, tmp)
+                if args.forms_only:
+                    r = choose_forms(key, read_table(args.out).get(key, dict(DEFAULT)), tmp)
+                    entries[key], details[str(key)] = r["best"], {"graph_ms": r["graph_ms"]}
+                else:
+                    entries[key], details[str(key)] = tune_class(key, tmp)
                 write_table(args.out, {**old, **entries})     # progress survives an interrupted run
     finally:
         os.unlink(tmp)

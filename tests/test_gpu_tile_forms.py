@@ -42,12 +42,13 @@ def rel(a, b):
     return np.abs(a - b).max() / np.abs(b).max()
 
 
-def _grid(shells, n_v, dph_par=-1, th_plane=0, rows=DEFAULT_ROWS, **kw):
+def _grid(shells, n_v, dph_par=-1, th_plane=0, rows=DEFAULT_ROWS, fuse=1, **kw):
     """A grid whose shells take the given forms (one table line per size)."""
     fd, path = tempfile.mkstemp(suffix=".txt", prefix="sg_forms_")
+    prec = kw.get("precision", ss.SG_PREC_FP64)
     with os.fdopen(fd, "w") as f:
         for (n_r, n_th) in sorted({(s[0], s[1]) for s in shells}):
-            f.write("%d %d %d 0 %s %d %d\n" % (n_r, n_th, n_v, rows, dph_par, th_plane))
+            f.write("%d %d %d %d %s %d %d %d\n" % (n_r, n_th, n_v, prec, rows, dph_par, th_plane, fuse))
     old = os.environ.get("SG_TUNING_FILE")
     os.environ["SG_TUNING_FILE"] = path
     try:
@@ -97,14 +98,16 @@ def test_theta_plane_tile(n_r, n_th, n_v, rows):
     gp.close()
 
 
+@pytest.mark.parametrize("prec", [ss.SG_PREC_FP64, ss.SG_PREC_FP32])
 @pytest.mark.parametrize("shells", [[(33, 32, 64, 1.8, 11.8)],
                                     [(17, 16, 32, 1.8, 11.8), (13, 9, 18, 2.0, 9.0), (17, 16, 32, 1.8, 11.8)]])
-def test_theta_plane_tile_in_steps(shells):
-    """Filtered RK4 steps with the plane tile (captured and eager) equal the
-    column tile's bit for bit."""
+def test_step_forms(shells, prec):
+    """Filtered RK4 steps (captured and eager) are the same bit for bit with
+    the plane or the column d_theta tile and with the three derivative
+    contractions of a stage in one launch or in three on forked streams."""
     out = []
-    for th_plane in (0, 1):
-        g = _grid(shells, 50, th_plane=th_plane)
+    for th_plane, fuse in ((0, 1), (1, 1), (0, 0), (1, 0)):
+        g = _grid(shells, 50, th_plane=th_plane, fuse=fuse, precision=prec)
         u = torch.zeros(g.state_size, dtype=torch.float64, device="cuda")
         parts = []
         for s in range(len(shells)):
@@ -120,7 +123,8 @@ def test_theta_plane_tile_in_steps(shells):
         assert torch.isfinite(ua).all() and torch.equal(ua, ub)
         out.append(ua)
         g.close()
-    assert torch.equal(out[0], out[1])
+    for k in range(1, len(out)):
+        assert torch.equal(out[0], out[k]), k
 
 
 @pytest.mark.parametrize("n_r,n_th", [(13, 10), (37, 7), (33, 32)])
