@@ -377,8 +377,10 @@ def main():
                                           "state_finite": res["state_finite"]},
            "step_roofline": {"bytes_per_step": graph_bytes, "achieved_GBps": graph_bytes / res["ms_per_step"] / 1e6,
                              "frac": graph_bytes / res["ms_per_step"] / 1e6 / HBM_PEAK_GBS,
-                             "model": "algorithmic FP64 bytes of the graph's launches: fused derivatives 32 B, "
-                                      "rhs stage 56 B (+128 B per point of gauge), filter 16+16 B + spectral"}}
+                             "model": "algorithmic FP64 bytes of one step: derivatives 32 B per stage (u read "
+                                      "once, three derivatives written, whether the graph runs them as one "
+                                      "launch or three), rhs stage 56 B (+128 B per point of gauge), "
+                                      "filter 16+16 B + spectral"}}
     if not args.no_timing:
         # second pass of K steps with HIP events around every launch on the
         # stream it runs on (eager launches; the three derivative contractions
