@@ -276,8 +276,11 @@ __global__ __launch_bounds__(256) void k_ftheta_bf3(int n_r, int n_th, int m_kee
     __bf16* x1h = x0l + 64 * ldx;
     __bf16* x1l = x1h + 64 * ldx;
     float* res = reinterpret_cast<float*>(x1l + 64 * ldx);   // [2][n_th][64]
-    const Blk3 b = xcd_block3();   // (column tile, m, set x shell), tiles of one range on one XCD
-    const int m = b.y;
+    // (column tile, 2 m + pass, set x shell), tiles of one range on one XCD; the
+    // two passes of a complex group at m > 0 read and write disjoint columns,
+    // so they are separate workgroups (the second exits for every other set)
+    const Blk3 b = xcd_block3();
+    const int m = b.y >> 1, pass_sel = b.y & 1;
     const FiltSet fs = sets[b.z % n_sets];
     const int shell = b.z / n_sets;
     const long long per_m = (long long)n_th * n_r;
@@ -303,7 +306,8 @@ __global__ __launch_bounds__(256) void k_ftheta_bf3(int n_r, int n_th, int m_kee
     const __bf16* Wl = Flo + fo;
     const bool mix = fs.cplx && m > 0;   // block-uniform
     const bool neg = G.sign < 0;          // F_+ = J F J for a negative spin
-    for (int pass = 0; pass < (mix ? 2 : 1); ++pass) {
+    if (pass_sel && !mix) return;
+    for (int pass = pass_sel; pass <= pass_sel; ++pass) {
         const float* xa;
         const float* xb = nullptr;
         bool rev0 = false, rev1 = false;
@@ -331,7 +335,6 @@ __global__ __launch_bounds__(256) void k_ftheta_bf3(int n_r, int n_th, int m_kee
             la[t] = (ip < n_th) ? xa[ip * (long long)n_r] : 0.0f;
             lb[t] = (ip < n_th && xb) ? xb[ip * (long long)n_r] : 0.0f;
         }
-        if (pass > 0) __syncthreads();
 #pragma unroll
         for (int t = 0; t < kPer; ++t) {
             const int ip = w + NW * t;
@@ -484,7 +487,7 @@ hipError_t launch_ftheta_bf3(const KShell& s, int count, const float* spec, floa
                              const FiltPlan& fp, int n_cols, int m_keep, hipStream_t st) {
     if (s.n_th > 64 || F.K < s.n_th || F.K % 16 || F.M % 32 || F.M < s.n_th || F.M > 64) return hipErrorInvalidValue;
     const long long cols = (long long)fp.max_groups * s.n_r;
-    const dim3 grid((unsigned)((cols + 63) / 64), (unsigned)(m_keep + 1), (unsigned)(fp.n_sets * count));
+    const dim3 grid((unsigned)((cols + 63) / 64), (unsigned)(2 * (m_keep + 1)), (unsigned)(fp.n_sets * count));
     const size_t shm = 4 * size_t(64) * (F.K + kBfPad) * sizeof(__bf16) + 2 * size_t(s.n_th) * 64 * sizeof(float);
     hipLaunchKernelGGL(k_ftheta_bf3, grid, dim3(256), shm, st, s.n_r, s.n_th, m_keep, n_cols, spec, spec2,
                        reinterpret_cast<const __bf16*>(F.hi), reinterpret_cast<const __bf16*>(F.lo), F.K, F.M,

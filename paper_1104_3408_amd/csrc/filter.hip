@@ -355,8 +355,11 @@ __global__ __launch_bounds__(64 * NW) void k_ftheta(int n_r, int n_th, int m_kee
                                                 const FiltSet* __restrict__ sets, int n_sets) {
     extern __shared__ double smd[];   // v0, v1: [n_th][64] in T
     T* sm = reinterpret_cast<T*>(smd);
-    const Blk3 b = xcd_block3();   // (column tile, m, set x shell), tiles of one range on one XCD
-    const int m = b.y;
+    // (column tile, 2 m + pass, set x shell), tiles of one range on one XCD; the
+    // two passes of a complex group at m > 0 read and write disjoint columns,
+    // so they are separate workgroups (the second exits for every other set)
+    const Blk3 b = xcd_block3();
+    const int m = b.y >> 1, pass_sel = b.y & 1;
     const FiltSet fs = sets[b.z % n_sets];
     const int shell = b.z / n_sets;
     const long long per_m = (long long)n_th * n_r;
@@ -383,7 +386,8 @@ __global__ __launch_bounds__(64 * NW) void k_ftheta(int n_r, int n_th, int m_kee
     T* v1 = sm + n_th * 64;
     const bool mix = fs.cplx && m > 0;   // block-uniform
     const bool neg = G.sign < 0;          // F_+ = J F J for a negative spin
-    for (int pass = 0; pass < (mix ? 2 : 1); ++pass) {
+    if (pass_sel && !mix) return;
+    for (int pass = pass_sel; pass <= pass_sel; ++pass) {
         const T* x0;
         const T* x1 = nullptr;
         bool rev0 = false, rev1 = false;
@@ -413,7 +417,6 @@ __global__ __launch_bounds__(64 * NW) void k_ftheta(int n_r, int n_th, int m_kee
             la[t] = (ip < n_th) ? x0[ip * (long long)n_r] : (T)0;
             lb[t] = (ip < n_th && x1) ? x1[ip * (long long)n_r] : (T)0;
         }
-        if (pass > 0) __syncthreads();
 #pragma unroll
         for (int t = 0; t < kFtPer; ++t) {
             const int ip = w + nw * t;
@@ -525,7 +528,7 @@ static hipError_t ftheta_t(const KShell& s, int count, const T* spec, T* spec2, 
                            int n_cols, int m_keep, hipStream_t st) {
     if (fp.R < 1 || fp.nw * fp.R < s.n_th || s.n_th > 64) return hipErrorInvalidValue;
     const long long cols = (long long)fp.max_groups * s.n_r;
-    const dim3 grid((unsigned)((cols + 63) / 64), (unsigned)(m_keep + 1), (unsigned)(fp.n_sets * count));
+    const dim3 grid((unsigned)((cols + 63) / 64), (unsigned)(2 * (m_keep + 1)), (unsigned)(fp.n_sets * count));
     const size_t shm = sizeof(T) * 2 * size_t(s.n_th) * 64;
 #define X(W_, R_)                                                                                               \
     if (fp.nw == W_ && fp.R == R_) {                                                                            \
