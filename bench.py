@@ -20,7 +20,9 @@ oracle (one shell per size class after one step, max and RMS); the other
 configurations (one 33x32x64 shell, one 49x48x96 shell in three precisions,
 8 shells of 65x64x128 with 58 fields) with their errors against the stored
 oracle evolutions after 1, 10 and 100 steps; and the oracle timed on the
-host on a bounded sample of the workload, on all cores and on one core.
+host on a bounded sample of the workload, on all cores and on one core; and
+the HBM bandwidth a plain device copy attains on this machine, beside the 8 TB/s
+specification the roofline fractions use.
 """
 import argparse
 import json
@@ -244,6 +246,28 @@ def against_stored(case, precisions, steps_wanted=None):
     return out
 
 
+def copy_bandwidth(mib=2048, reps=10):
+    """Attainable HBM bandwidth on this machine: a device-to-device copy of `mib`
+    MiB (as many bytes read as written), timed with HIP events; reads plus
+    writes per second."""
+    import torch
+    src = torch.ones(mib * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(reps):
+        dst.copy_(src)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / reps
+    out = {"GBps": 2 * src.numel() * 8 / ms / 1e6, "bytes_each_way": src.numel() * 8, "ms": ms,
+           "frac_of_spec": 2 * src.numel() * 8 / ms / 1e6 / HBM_PEAK_GBS}
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
+
+
 def fft_vs_matmul(reps=20):
     """d_phi by the library's Fourier-matrix contraction against an FFT route
     (torch.fft on ROCm: real FFT along phi, multiply by i m with the Nyquist
@@ -423,6 +447,8 @@ def main():
 
     ones = {"fp64": one64}
     if not args.no_variants:
+        out["measured_copy_bandwidth"] = copy_bandwidth()
+        log("copy bandwidth %.0f GB/s" % out["measured_copy_bandwidth"]["GBps"])
         var = {}
         for prec in (ss.SG_PREC_FP32, ss.SG_PREC_BF16X3):
             r, gm, um, _, onem = run_form(shells, n_v, prec, args.steps, args.warmup, seed0, keep=reps)

@@ -82,7 +82,9 @@ typedef struct {
                          state at the start of each rk_step call, refreshed every
                          64 steps);
                          d_r, the rhs and the RK state stay FP64.  SG_PREC_BF16X3:
-                         as SG_PREC_FP32, but the theta and phi contractions run on
+                         as SG_PREC_FP32, but the theta and phi derivative
+                         contractions and the filter's reduced-precision part (phi
+                         analysis, theta filter, phi synthesis of u - u_ref) run on
                          the matrix cores with each operand split into two
                          bfloat16 parts, W x ~ W_hi x_hi + W_hi x_lo + W_lo x_hi
                          accumulated in FP32 (about 2^-16 of |W||x| per product);
@@ -112,8 +114,12 @@ typedef struct {
  * Yninc/Yndec and uploaded once.  gauge_H: optional device array with the
  * static gauge source H_a (4 variables per point, same per-shell layout as a
  * 4-field state); when given, its Cartesian derivatives are computed here
- * (null stream, synchronous).  On success *out owns device memory released
- * by shell_grid_destroy. */
+ * (null stream, synchronous).  Tile shapes and kernel forms per shell size
+ * and precision come from a text table read here (the file named by the
+ * environment variable SG_TUNING_FILE, else tuning.txt beside the library;
+ * defaults for sizes it does not list).  They change the speed; only the
+ * d_phi form (circulant or parity) also changes the order of the rounding.
+ * On success *out owns device memory released by shell_grid_destroy. */
 sg_status shell_grid_create(const sg_shell_desc* shells, int n_shells, const sg_options* opt,
                             const double* gauge_H, sg_grid** out);
 
