@@ -554,6 +554,7 @@ sg_status shell_grid_create(const sg_shell_desc* shells, int n_shells, const sg_
             op.n_in = n;
             op.n_out = n;
             op.circ = 1;
+            op.mfma = H.tune.dph_mfma && n % 16 == 0 && n <= 128;   // FP64 launches on the matrix cores
             if (blocked_shape(n, rows, op.R, op.passes) != 0) return hipErrorInvalidValue;
             std::vector<double> dv(size_t(2 * n + 4 * op.R * op.passes), 0.0);
             for (int t = 0; t < 2 * n; ++t) dv[t] = col[((t - n) % n + n) % n];

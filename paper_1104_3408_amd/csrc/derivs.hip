@@ -397,6 +397,74 @@ __global__ __launch_bounds__(1024) void k_axis(const I* __restrict__ in, O* __re
     axis_tile<R, I, T, O, CIRC>(blockIdx.x, blockIdx.y, in, out, Wb, n_in, n_out, ncol, center, smd);
 }
 
+// d_phi in FP64 on the matrix cores (v_mfma_f64_16x16x4f64), for N_phi a
+// multiple of 16: a dense N_phi x N_phi contraction of 2 N_phi flops per
+// field-point, which at N_phi >= 96 keeps the vector units busier than the
+// memory system.  Workgroup = 64 (theta, r) columns of one field (blockIdx.x
+// column tile, blockIdx.y field) staged in LDS after the FP64 circle-mean
+// removal of axis_tile; wave w forms output rows 16 w .. 16 w + 15 for the
+// four 16-column blocks, accumulating over the inputs four at a time.
+// Operand layout of the instruction (checked on the device with a one-wave
+// probe): lane l feeds A[l % 16][l / 16] and B[l / 16][l % 16] and holds
+// D[4 v + l / 16][l % 16] in item v of its result.  A[i][k] = D_phi[16 w + i][k0
+// + k] = dv[N + 16 w + i - k0 - k] from the doubled circulant column dv,
+// staged in LDS beside the tile (2 N values).
+constexpr int kMfmaCols = 64;
+
+__global__ __launch_bounds__(512) void k_dphi_mfma(const double* __restrict__ in, double* __restrict__ out,
+                                                   const double* __restrict__ dv, int n, long long ncol) {
+    extern __shared__ double smd[];
+    double* sm = smd;                        // [n][64]: value - column mean
+    const int lane = threadIdx.x & 63;
+    const int w = wave_id();
+    const int nw = blockDim.x >> 6;          // = n / 16
+    double* spart = smd + n * kMfmaCols;     // [nw][64]: partial sums
+    double* sdv = spart + nw * kMfmaCols;    // [2n]: the doubled circulant column
+    for (int t = threadIdx.x; t < 2 * n; t += blockDim.x) sdv[t] = dv[t];
+    const long long c0 = (long long)blockIdx.x * kMfmaCols;
+    const int nc = (int)min((long long)kMfmaCols, ncol - c0);
+    const long long f = blockIdx.y;
+    const double* src = in + f * n * ncol + c0;
+    const int lc = lane < nc ? lane : 0;   // an in-bounds column for every lane
+    constexpr int kPer = 16;               // rows per thread: n / nw
+    double v[kPer];
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) v[t] = src[(long long)(w + nw * t) * ncol + lc];
+    double part = 0.0;
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) part += v[t];
+    spart[w * kMfmaCols + lane] = part;
+    __syncthreads();
+    double mc = 0.0;
+    for (int q = 0; q < nw; ++q) mc += spart[q * kMfmaCols + lane];
+    mc /= n;
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) sm[(w + nw * t) * kMfmaCols + lane] = v[t] - mc;
+    __syncthreads();
+    typedef double v4d __attribute__((ext_vector_type(4)));
+    v4d acc[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) acc[cb] = v4d{0.0, 0.0, 0.0, 0.0};
+    const int li = lane & 15, lk = lane >> 4;
+    const double* arow = sdv + n + 16 * w + li - lk;   // A[li][lk] at step k0: arow[-k0]
+    #pragma unroll 4
+    for (int k0 = 0; k0 < n; k0 += 4) {
+        const double a = arow[-k0];
+        const double* brow = sm + (k0 + lk) * kMfmaCols + li;
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, brow[16 * cb], acc[cb], 0, 0, 0);
+    }
+    double* dst = out + f * n * ncol + c0;
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+        const int col = 16 * cb + li;
+        if (col < nc) {
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) dst[(long long)(16 * w + 4 * vv + lk) * ncol + col] = acc[cb][vv];
+        }
+    }
+}
+
 // Contractions along phi in the parity form (MODE: kParAna, kParSyn,
 // kParDphi).  About phi = 0 cos is even and sin odd, and the Fourier
 // derivative matrix FD[q][c] = v[(q - c) mod N] has v odd, so with
@@ -723,6 +791,16 @@ static hipError_t axis_t(const AxisOp& op, const T* Wb, const I* in, O* out, lon
         }
         return hipGetLastError();
     }
+    if constexpr (sizeof(I) == sizeof(double) && sizeof(T) == sizeof(double) && sizeof(O) == sizeof(double)) {
+        if (op.mfma && op.circ && center) {   // FP64 d_phi on the matrix cores
+            const int n = op.n_in;
+            if (n % 16 || n / 16 > 8 || n / 16 < 1) return hipErrorInvalidValue;
+            const size_t shm_m = sizeof(double) * (size_t(n) * kMfmaCols + size_t(n / 16) * kMfmaCols + 2 * size_t(n));
+            hipLaunchKernelGGL(k_dphi_mfma, dim3((unsigned)((ncol + kMfmaCols - 1) / kMfmaCols), (unsigned)n_fields),
+                               dim3(64 * (n / 16)), shm_m, st, in, out, Wb, n, ncol);
+            return hipGetLastError();
+        }
+    }
     const size_t shm = sizeof(T) * size_t(op.n_in) * 64 + size_t(4 * op.passes) * 64 * sizeof(double);
     switch (op.R) {
 #define X(R)                                                                                                   \
@@ -760,7 +838,7 @@ template <typename T, typename O>
 static hipError_t derivs3_t(const KShell& s, const AxisOp& dph, const T* Wph, const T* Hsb,
                             const double* in, double* out_r, O* out_th, O* out_ph, int n_fields, hipStream_t st) {
     const int nw = s.Dr_nw;
-    if (s.Hth_nw != nw || 4 * dph.passes != nw || (dph.par != 3 && !dph.circ) || dph.n_in != s.n_ph ||
+    if (s.Hth_nw != nw || 4 * dph.passes != nw || (dph.par != 3 && !dph.circ) || dph.mfma || dph.n_in != s.n_ph ||
         s.Dr_R > kFusedMaxR || s.Hth_R > kFusedMaxRth || dph.R > (dph.circ ? kFusedMaxRcirc : kFusedMaxR))
         return hipErrorNotSupported;   // shapes disagree: the caller launches the three kernels
     if (s.n_th > nw * kThMaxPerThread || dph.n_in > kAxisMaxIn) return hipErrorInvalidValue;

@@ -68,6 +68,9 @@ struct AxisOp {
     // of axis_par_tile (derivs.hip), keeping orders m <= m_keep; R and passes
     // then block the row pairs (a_m, b_m), resp. (A_j, B_j), j <= N_phi / 2
     int par = 0, m_keep = 0;
+    // mfma: the FP64 circulant d_phi on the matrix cores (k_dphi_mfma; N a
+    // multiple of 16, at most 128)
+    int mfma = 0;
 };
 
 // Largest number of output rows one wave accumulates, and of waves in one
@@ -110,6 +113,7 @@ struct Tune {
     int dph_par = -1;   // d_phi form: 0 circulant window, 1 parity; -1: parity in FP32 modes only
     int th_plane = 0;   // FP64 d_theta tile: 0 64 columns, 1 a meridian plane pair
     int fuse = 1;       // the three derivative contractions as one launch where the shapes allow
+    int dph_mfma = 0;   // FP64 circulant d_phi on the matrix cores (N_phi a multiple of 16)
 };
 // The table entry for this shell size, or the defaults; *source names where
 // it came from (the table's path, or "defaults").

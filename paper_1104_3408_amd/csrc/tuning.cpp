@@ -5,9 +5,10 @@
 // table, one line per (N_r, N_theta, n_fields, precision):
 //
 //   # n_r n_theta n_fields precision dr_rows th_rows dph_rows ana_rows syn_rows filt_waves dph_par th_plane fuse
-//   49 48 50 0 9 3 13 11 8 4 0 1 0
+//   #   dph_mfma
+//   49 48 50 0 9 3 13 11 8 4 0 1 0 1
 //
-// (the last three columns may be left out: defaults)
+// (the last four columns may be left out: defaults)
 //
 // shell_grid_create reads the table on every call: from the path in the
 // environment variable SG_TUNING_FILE if set, else tuning.txt beside the
@@ -42,7 +43,7 @@ bool valid(const Tune& t) {
     for (int r : {t.dr_rows, t.th_rows, t.dph_rows, t.ana_rows, t.syn_rows})
         if (r < 1 || r > kMaxRows) return false;
     return (t.filt_waves == 4 || t.filt_waves == 8 || t.filt_waves == 16) && t.dph_par >= -1 && t.dph_par <= 1 &&
-           (t.th_plane == 0 || t.th_plane == 1) && (t.fuse == 0 || t.fuse == 1);
+           (t.th_plane == 0 || t.th_plane == 1) && (t.fuse == 0 || t.fuse == 1) && (t.dph_mfma == 0 || t.dph_mfma == 1);
 }
 
 }  // namespace
@@ -60,9 +61,9 @@ Tune lookup_tuning(int n_r, int n_theta, int n_fields, int precision, std::strin
         if (line[0] == '#') continue;
         int a, b, c, d;
         Tune t;
-        const int n = std::sscanf(line, "%d %d %d %d %d %d %d %d %d %d %d %d %d", &a, &b, &c, &d, &t.dr_rows,
+        const int n = std::sscanf(line, "%d %d %d %d %d %d %d %d %d %d %d %d %d %d", &a, &b, &c, &d, &t.dr_rows,
                                   &t.th_rows, &t.dph_rows, &t.ana_rows, &t.syn_rows, &t.filt_waves, &t.dph_par,
-                                  &t.th_plane, &t.fuse);
+                                  &t.th_plane, &t.fuse, &t.dph_mfma);
         if (n < 10) continue;
         if (a == n_r && b == n_theta && c == n_fields && d == precision && valid(t)) {
             found = t;

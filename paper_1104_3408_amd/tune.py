@@ -19,7 +19,8 @@ Candidate values are target rows per wave (blocked_shape turns a target into
 rows per wave and 8, 12 or 16 waves per workgroup; targets giving the same
 shape are timed once), 4, 8 or 16 waves per workgroup for the theta filter,
 the d_phi form (circulant window or parity) and, in FP64, the d_theta tile
-(64 columns or a meridian plane pair).
+(64 columns or a meridian plane pair) and the circulant d_phi on the matrix
+cores or the vector units.
 """
 import argparse
 import os
@@ -28,13 +29,14 @@ import tempfile
 import time
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-FIELDS = ["dr_rows", "th_rows", "dph_rows", "ana_rows", "syn_rows", "filt_waves", "dph_par", "th_plane", "fuse"]
+FIELDS = ["dr_rows", "th_rows", "dph_rows", "ana_rows", "syn_rows", "filt_waves", "dph_par", "th_plane", "fuse",
+          "dph_mfma"]
 DEFAULT = {"dr_rows": 9, "th_rows": 4, "dph_rows": 8, "ana_rows": 8, "syn_rows": 8, "filt_waves": 8, "dph_par": -1,
-           "th_plane": 0, "fuse": 1}
+           "th_plane": 0, "fuse": 1, "dph_mfma": 0}
 # kernel class (KERNEL_CLASSES order of the binding) timed for each field
 FIELD_CLASS = {"dr_rows": "d_r", "th_rows": "d_theta", "dph_rows": "d_phi", "ana_rows": "filter_phi_analysis",
                "syn_rows": "filter_phi_synthesis", "filt_waves": "filter_theta", "dph_par": "d_phi",
-               "th_plane": "d_theta"}
+               "th_plane": "d_theta", "dph_mfma": "d_phi"}
 ROW_TARGETS = (3, 4, 5, 6, 8, 9, 11, 13, 16)
 # shell sizes of the workloads: (N_r, N_theta, n_fields, shells per batch, r_max)
 CLASSES = {17: (17, 16, 50, 16, 11.8), 25: (25, 24, 50, 16, 11.8), 33: (33, 32, 50, 16, 11.8),
@@ -153,6 +155,8 @@ def tune_class(key, table_path):
             cands = [0, 1]
         elif field == "th_plane":
             cands = [0, 1] if prec == 0 else [0]     # the plane tile is the FP64 form
+        elif field == "dph_mfma":                    # FP64 circulant d_phi on the matrix cores
+            cands = [0, 1] if prec == 0 and (2 * n_th) % 16 == 0 and not dph_parity(best, prec) else [0]
         else:
             shapes = {}
             for t in ROW_TARGETS:

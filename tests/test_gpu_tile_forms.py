@@ -7,7 +7,10 @@ oracle (FP64 bar 1e-12) and with the default form:
   filtered steps agree bit for bit, in the one-launch form of the three
   derivative contractions and in the separate launches of the timing mode;
   shapes with odd N_theta, N_r above one 64-lane chunk and the 58-field form;
-* d_phi in the parity form (dph_par 1) in FP64 against the oracle.
+* d_phi in the parity form (dph_par 1) in FP64 against the oracle;
+* the FP64 circulant d_phi on the matrix cores (dph_mfma 1; N_phi = 16 ...
+  128, ragged column tiles) against the oracle, and whole filtered steps with
+  it (captured and eager) equal to each other bit for bit.
 """
 import os
 import tempfile
@@ -42,13 +45,13 @@ def rel(a, b):
     return np.abs(a - b).max() / np.abs(b).max()
 
 
-def _grid(shells, n_v, dph_par=-1, th_plane=0, rows=DEFAULT_ROWS, fuse=1, **kw):
+def _grid(shells, n_v, dph_par=-1, th_plane=0, rows=DEFAULT_ROWS, fuse=1, dph_mfma=0, **kw):
     """A grid whose shells take the given forms (one table line per size)."""
     fd, path = tempfile.mkstemp(suffix=".txt", prefix="sg_forms_")
     prec = kw.get("precision", ss.SG_PREC_FP64)
     with os.fdopen(fd, "w") as f:
         for (n_r, n_th) in sorted({(s[0], s[1]) for s in shells}):
-            f.write("%d %d %d %d %s %d %d %d\n" % (n_r, n_th, n_v, prec, rows, dph_par, th_plane, fuse))
+            f.write("%d %d %d %d %s %d %d %d %d\n" % (n_r, n_th, n_v, prec, rows, dph_par, th_plane, fuse, dph_mfma))
     old = os.environ.get("SG_TUNING_FILE")
     os.environ["SG_TUNING_FILE"] = path
     try:
@@ -138,4 +141,37 @@ def test_phi_parity_form_fp64(n_r, n_th):
         got = _derivs(g, dev(u), timing).cpu().numpy().reshape((3,) + u.shape)
         for d in range(3):
             assert rel(got[d], ref[d]) < TOL, (timing, d, rel(got[d], ref[d]))
+    g.close()
+
+
+@pytest.mark.parametrize("n_r,n_th", [(13, 8), (37, 24), (33, 32), (49, 48), (21, 64)])
+def test_phi_matrix_cores_fp64(n_r, n_th):
+    desc = (n_r, n_th, 2 * n_th, 1.8, 11.8)
+    sh = Shell(*desc)
+    u = np.random.default_rng(5 * n_r + n_th).standard_normal((50,) + sh.shape)
+    g = _grid([desc], 50, dph_par=0, dph_mfma=1, fuse=0)
+    ref = od.coordinate_derivs(u, sh)
+    for timing in (False, True):
+        got = _derivs(g, dev(u), timing).cpu().numpy().reshape((3,) + u.shape)
+        for d in range(3):
+            assert rel(got[d], ref[d]) < TOL, (timing, d, rel(got[d], ref[d]))
+    g.close()
+
+
+def test_steps_with_phi_on_matrix_cores():
+    shells = [(33, 32, 64, 1.8, 11.8), (17, 16, 32, 1.8, 11.8)]
+    g = _grid(shells, 50, dph_par=0, dph_mfma=1, fuse=1)   # the one-launch form steps aside for it
+    u = torch.zeros(g.state_size, dtype=torch.float64, device="cuda")
+    parts = []
+    for s in range(len(shells)):
+        r, th, ph = g.coords(s)
+        parts.append(inputs.perturbed_kerr_schild(21 + s, r, th, ph).ravel())
+    g.kerr_schild_data(dev(np.concatenate(parts)), u)
+    ua, ub = u.clone(), u.clone()
+    g.rk_step(ua, 3)
+    g.enable_timing(True)
+    g.rk_step(ub, 3)
+    g.enable_timing(False)
+    torch.cuda.synchronize()
+    assert torch.isfinite(ua).all() and torch.equal(ua, ub)
     g.close()
