@@ -13,10 +13,17 @@ right-hand side are carried out in that mode's rounding (oracle.rounding;
 everything else stays the oracle's FP64 code): the prediction of the state a
 reduced-precision run must reach, written to oracle_<case>_<mode>.npz.
 
+The case large8_shell0 is the first shell of the 8-shell 58-field batch
+(65 x 64 x 128 on [1.8, 21.8], perturbation seed 5000, gauge fields seed
+6000; the gauge source H_a and its rate Q_a are evolved, App. A.1 with
+reading R15): it stores, besides the sampled state, the constraint norms
+(max and RMS of C_a and C_iab, App. A.1) after every step from t = 0.
+
 Usage: python tests/golden/make_oracle_evolutions.py [--mode MODE] [--steps N] CASE [CASE ...]
-Cases: shell17_100, shell33_100, shell49_100 (see CASES).  Each writes
-tests/golden/oracle_<case>[_<mode>].npz; the 49 x 48 x 96 case takes about
-an hour per mode.  --steps N keeps only the stored step counts <= N.
+Cases: shell17_100, shell33_100, shell49_100, large8_shell0 (see CASES).
+Each writes tests/golden/oracle_<case>[_<mode>].npz; the 49 x 48 x 96 case
+takes about an hour per mode, large8_shell0 several minutes per step.
+--steps N keeps only the stored step counts <= N.
 """
 import argparse
 import os
@@ -31,14 +38,17 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 from oracle.grid import Shell, courant_dt            # noqa: E402
 from oracle import initial_data as oid              # noqa: E402
 from oracle.evolve import Evolution                 # noqa: E402
+from oracle import ghg                              # noqa: E402
 from oracle.rounding import RoundedEvolution        # noqa: E402
 from paper_1104_3408_amd import inputs              # noqa: E402
 
-# name: (N_r, N_theta, r_min, r_max, perturbation seed, stored step counts)
+# name: (N_r, N_theta, r_min, r_max, perturbation seed, stored step counts[,
+# gauge-field seed for the 58-field form])
 CASES = {
     "shell17_100": (17, 16, 1.8, 11.8, 2, (1, 10, 100)),
     "shell33_100": (33, 32, 1.8, 11.8, 2, (1, 10, 100)),
     "shell49_100": (49, 48, 1.8, 11.8, 3, (1, 100)),
+    "large8_shell0": (65, 64, 1.8, 21.8, 5000, (1, 5, 10), 6000),
 }
 N_RANDOM = 30000
 
@@ -57,17 +67,23 @@ def sample_indices(shape):
 
 
 def run(name, mode="fp64", max_steps=None):
-    n_r, n_th, r0, r1, seed, saves = CASES[name]
+    n_r, n_th, r0, r1, seed, saves = CASES[name][:6]
+    gauge_seed = CASES[name][6] if len(CASES[name]) > 6 else None
     if max_steps is not None:
         saves = tuple(n for n in saves if n <= max_steps)
     sh = Shell(n_r, n_th, 2 * n_th, r0, r1)
     g10 = inputs.perturbed_kerr_schild(seed, sh.r, sh.theta, sh.phi)
     u0 = oid.first_order_data(g10, sh)
     H, dH = oid.static_gauge(u0, sh)
+    n_v = 50
+    if gauge_seed is not None:     # 58 fields: H_a = -Gamma_a + dH, Q_a evolved with the state
+        dHp, Q = inputs.gauge_perturbation(gauge_seed, sh.r, sh.theta, sh.phi)
+        u0 = np.concatenate([u0, H + dHp, Q])
+        H, dH, n_v = None, None, 58
     if mode == "fp64":
-        ev = Evolution(sh, 50, H, dH, "Yn", 4)
+        ev = Evolution(sh, n_v, H, dH, "Yn", 4)
     else:
-        ev = RoundedEvolution(sh, 50, H, dH, "Yn", 4, mode=mode)
+        ev = RoundedEvolution(sh, n_v, H, dH, "Yn", 4, mode=mode)
     dt = courant_dt(sh)
     idx = sample_indices(u0.shape)
     out = {"idx": idx, "dt": np.float64(dt), "shape": np.array(u0.shape, dtype=np.int64),
@@ -75,8 +91,17 @@ def run(name, mode="fp64", max_steps=None):
            "seed": np.int64(seed), "radii": np.array([r0, r1]), "mode": np.array(mode)}
     u = u0
     t0 = time.time()
+    norms = []
+
+    def constraint_norms(v):
+        return ghg.constraint_norms(*ghg.constraints(v, np.array(ev.cart_derivs(v)), H))
+    if gauge_seed is not None:
+        norms.append(constraint_norms(u0))
     for n in range(1, max(saves) + 1):
         u = ev.rk4_step(u, dt)
+        if gauge_seed is not None:
+            norms.append(constraint_norms(u))
+            out["constraint_norms"] = np.array(norms)       # [step][max C_a, rms C_a, max C_iab, rms C_iab]
         if n in saves:
             ch = u - u0
             out["vals_%d" % n] = u.ravel()[idx]
@@ -84,9 +109,11 @@ def run(name, mode="fp64", max_steps=None):
             out["rms_u_%d" % n] = np.float64(np.sqrt(np.mean(u ** 2)))
             out["max_du_%d" % n] = np.float64(np.abs(ch).max())
             out["rms_du_%d" % n] = np.float64(np.sqrt(np.mean(ch ** 2)))
+            # written at every stored step count, so an interrupted run keeps what it reached
+            out["steps"] = np.array([m for m in saves if m <= n], dtype=np.int64)
+            suffix = "" if mode == "fp64" else "_" + mode
+            np.savez(os.path.join(HERE, "oracle_%s%s.npz" % (name, suffix)), **out)
         print("%s %s: step %d, %.0f s" % (name, mode, n, time.time() - t0), flush=True)
-    suffix = "" if mode == "fp64" else "_" + mode
-    np.savez(os.path.join(HERE, "oracle_%s%s.npz" % (name, suffix)), **out)
 
 
 if __name__ == "__main__":
