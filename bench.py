@@ -19,7 +19,9 @@ contractions) with their speed-up; the error of every form against the CPU
 oracle (one shell per size class after one step, max and RMS); the other
 configurations (one 33x32x64 shell, one 49x48x96 shell in three precisions,
 8 shells of 65x64x128 with 58 fields) with their errors against the stored
-oracle evolutions after 1, 10 and 100 steps; and the oracle timed on the
+oracle evolutions after 1, 10 and 100 steps; four nested shells coupled at
+their shared spheres against the same shells uncoupled, and the Y and Yg
+filters against Yn on the 33x32x64 shell; and the oracle timed on the
 host on a bounded sample of the workload, on all cores and on one core; and
 the HBM bandwidth a plain device copy attains on this machine, beside the 8 TB/s
 specification the roofline fractions use.
@@ -131,8 +133,9 @@ def profiled_traffic(workload, cls):
     return val if have == want else None
 
 
-def initial_state(g, shells, n_v, seed0):
-    """Seeded perturbed Kerr-Schild data on every shell (seed0 + shell index;
+def initial_state(g, shells, n_v, seed0, one_seed=False):
+    """Seeded perturbed Kerr-Schild data on every shell (seed0 + shell index,
+    or seed0 for all with one_seed: one smooth field across nested shells;
     gauge fields seed0 + 1000 + index), built by the library."""
     import numpy as np
     import torch
@@ -140,7 +143,7 @@ def initial_state(g, shells, n_v, seed0):
     g10, extra = [], []
     for k in range(len(shells)):
         r, th, ph = g.coords(k)
-        g10.append(inputs.perturbed_kerr_schild(seed0 + k, r, th, ph).ravel())
+        g10.append(inputs.perturbed_kerr_schild(seed0 + (0 if one_seed else k), r, th, ph).ravel())
         if n_v == 58:
             dH, Q = inputs.gauge_perturbation(seed0 + 1000 + k, r, th, ph)
             extra.append(np.concatenate([dH, Q]).ravel())
@@ -160,14 +163,14 @@ def class_representatives(shells):
     return out
 
 
-def run_form(shells, n_v, precision, steps, warmup, seed0, keep=()):
+def run_form(shells, n_v, precision, steps, warmup, seed0, keep=(), filter="Yn", flags=0, one_seed=False):
     """One precision form of a workload: initial data, one step from it (the
     states of the shells in `keep` are returned on the host, for the error
     against the oracle), then warmup and `steps` timed steps (graph replay)."""
     import torch
     from paper_1104_3408_amd import shellspec as ss
-    g = ss.ShellGrid(shells, n_fields=n_v, filter="Yn", n_f=4, courant=4.0, precision=precision)
-    u, g10 = initial_state(g, shells, n_v, seed0)
+    g = ss.ShellGrid(shells, n_fields=n_v, filter=filter, n_f=4, courant=4.0, precision=precision, flags=flags)
+    u, g10 = initial_state(g, shells, n_v, seed0, one_seed)
     one = {}
     if keep:
         u1 = u.clone()
@@ -489,6 +492,28 @@ def main():
                 gm.close()
                 del um, gm
                 torch.cuda.empty_cache()
+        # the survey's next rows, measured: nested shells (four 33x32x64 shells
+        # on [1.8, 17.8] coupled at their shared spheres against the same four
+        # shells uncoupled) and the scalar Y and graded Yg filters on the
+        # 33x32x64 shell against Yn
+        nest = [(33, 32, 64, 1.8 + 4.0 * k, 5.8 + 4.0 * k) for k in range(4)]
+        other["nested4"] = {"description": "4 perturbed Kerr-Schild shells 33x32x64 on [1.8, 5.8, 9.8, 13.8, 17.8], "
+                                           "50 fields, Yn n_f=4, FP64, one time step for the chain"}
+        for name, flags in (("coupled", ss.SG_NESTED), ("independent", 0)):
+            r, gm, um, _, _ = run_form(nest, 50, ss.SG_PREC_FP64, args.steps, args.warmup, 7000, flags=flags,
+                                       one_seed=True)
+            other["nested4"][name] = r
+            gm.close()
+            del um, gm
+        s33 = inputs.workload_shells("ks33")[0]
+        other["filters_33"] = {"description": DESCRIPTIONS["ks33"] + ", filter kind varied"}
+        for kind in ("Y", "Yg"):
+            r, gm, um, _, _ = run_form(s33, 50, ss.SG_PREC_FP64, args.steps, args.warmup,
+                                       inputs.WORKLOAD_SEED["ks33"], filter=kind)
+            other["filters_33"][kind] = r
+            gm.close()
+            del um, gm
+        torch.cuda.empty_cache()
         out["other_configs"] = other
         out["fft_vs_matmul_dphi"] = fft_vs_matmul()
         log("FFT comparison done")
