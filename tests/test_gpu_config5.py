@@ -116,33 +116,42 @@ def test_first_shell_against_stored_oracle(form):
     g.close()
 
 
-def test_thousand_steps_constraint_norms():
-    traj = {}
-    for form, prec in PRECS.items():
-        g, shells, u = _batch(prec)
-        rows = [_norms(g, u, len(shells))]
-        for _ in range(100):
-            g.rk_step(u, 10)
-            rows.append(_norms(g, u, len(shells)))
-        assert torch.isfinite(u).all(), form
-        u_max = float(u.abs().max())
-        traj[form] = np.array(rows)                    # [sample][shell][4]
-        g.close()
-        del u
-        torch.cuda.empty_cache()
-        assert np.isfinite(traj[form]).all(), form
-        t = traj[form].max(axis=1)
-        print("%s: max over shells every 100 steps, (max C_a, rms C_a, max C_iab, rms C_iab):" % form, flush=True)
-        for s in range(0, t.shape[0], 10):
-            print("  step %4d: %s" % (10 * s, " ".join("%.3e" % x for x in t[s])), flush=True)
-    f64 = traj["fp64"]
-    mx = {form: t.max(axis=1) for form, t in traj.items()}     # [sample][4], max over shells
-    assert mx["fp64"][-1, 0] < mx["fp64"][0, 0] and mx["fp64"][:, 2].max() < 1e-9
-    for form, t in mx.items():
-        for c in (0, 2):
-            assert t[-1, c] <= 2.0 * t[50, c], (form, c, t[50, c], t[-1, c])
+TRAJ = {}   # form -> (norms [sample][shell][4] every 10 steps, max |u| at the end)
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32", "bf16x3"])
+def test_thousand_steps(form):
+    """1000 steps of the batch in one form: finite norms, none growing over
+    the last 500 steps; FP64's C_a damped and its C_iab below 1e-9."""
+    g, shells, u = _batch(PRECS[form])
+    rows = [_norms(g, u, len(shells))]
+    for _ in range(100):
+        g.rk_step(u, 10)
+        rows.append(_norms(g, u, len(shells)))
+    assert torch.isfinite(u).all(), form
+    u_max = float(u.abs().max())
+    g.close()
+    del u
+    torch.cuda.empty_cache()
+    traj = np.array(rows)
+    TRAJ[form] = (traj, u_max)
+    assert np.isfinite(traj).all(), form
+    t = traj.max(axis=1)                                # max over shells
+    print("%s: max over shells every 100 steps, (max C_a, rms C_a, max C_iab, rms C_iab):" % form, flush=True)
+    for k in range(0, t.shape[0], 10):
+        print("  step %4d: %s" % (10 * k, " ".join("%.3e" % x for x in t[k])), flush=True)
+    for c in (0, 2):
+        assert t[-1, c] <= 2.0 * t[50, c], (form, c, t[50, c], t[-1, c])
+    if form == "fp64":
+        assert t[-1, 0] < t[0, 0] and t[:, 2].max() < 1e-9
+
+
+def test_thousand_steps_mixed_against_fp64():
+    if any(f not in TRAJ for f in PRECS):
+        pytest.skip("needs the three 1000-step runs of this module")
+    f64, _ = TRAJ["fp64"]
     for form in ("fp32", "bf16x3"):
-        m = traj[form]
+        m, u_max = TRAJ[form]
         unit = {"fp32": 2.0 ** -24, "bf16x3": 2.0 ** -16}[form]
         d_ca = np.abs(m[..., 0] - f64[..., 0]).max()
         c_iab = m[..., 2].max()
