@@ -187,16 +187,20 @@ sg_status ghg_constraints_static(const sg_grid* g, const double* u, const double
 /* Right-hand side d_t u of the first-order GHG system (App. A.1 eqs. gdot,
  * Phidot, Pidot with gamma_0 = gamma_2 = 1, gamma_1 = -1), with the
  * freezing-incoming boundary operator (App. A.3) applied on the outermost
- * sphere k = N_r - 1.  du_cart: Cartesian derivatives of u in the derivative
- * layout, or NULL to compute them here.  rhs must not alias u. */
+ * sphere k = N_r - 1 (of each shell; with SG_NESTED only of the outermost
+ * shell of a chain, and the two copies of a shared sphere get one value,
+ * each characteristic field from its upwind side).  du_cart: Cartesian
+ * derivatives of u in the derivative layout, or NULL to compute them here.
+ * rhs must not alias u. */
 sg_status ghg_rhs(sg_grid* g, const double* u, const double* du_cart, double* rhs,
                   sg_stream_t stream);
 
 /* n_steps classical RK4 steps of the method of lines (Sec. 2.5), u in place:
  * four right-hand-side evaluations (derivatives, rhs, boundary operator),
  * then the filter after each full step.  dt: host array with one time step
- * per shell (finite and > 0, else SG_EINVAL), or NULL for each shell's Courant
- * step.  One step is captured
+ * per shell (finite and > 0, else SG_EINVAL; shells coupled by SG_NESTED must
+ * share one, else SG_EINVAL), or NULL for each shell's Courant step (the
+ * chain's smallest for coupled shells).  One step is captured
  * into a HIP graph (on a private stream, re-captured when u or dt change)
  * and replayed n_steps times on the given stream, unless SG_NO_GRAPH is set
  * or kernel timing is enabled.  With SG_CHECK_FINITE the

@@ -590,6 +590,10 @@ __global__ __launch_bounds__(256) void k_constraint_norms(const double* __restri
 // mean.  The copies' stage outputs were formed from the raw right-hand
 // sides; they are corrected here by the stage coefficients times the
 // difference (stage 0: the output is the right-hand side).
+// Thread (angular point, pair q): blockIdx.y = q for the ten symmetric pairs,
+// q = 10 for the gauge fields of the 58-field form; every load of a thread is
+// issued before the first use (a patch launch is a few dozen workgroups, so
+// the time is the threads' chains of memory latencies).
 __global__ __launch_bounds__(256) void k_patch(KShell sa, KShell sb, const double* __restrict__ ua,
                                                const double* __restrict__ ka, const double* __restrict__ kb,
                                                double* __restrict__ out_a, double* __restrict__ acc_a,
@@ -597,87 +601,123 @@ __global__ __launch_bounds__(256) void k_patch(KShell sa, KShell sb, const doubl
                                                int stage) {
     const long long nang = (long long)sa.n_th * sa.n_ph;
     const long long ang = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int q = blockIdx.y;
     if (ang >= nang) return;
-    const int i = (int)(ang % sa.n_th), j = (int)(ang / sa.n_th);
     const long long pa = (long long)(sa.n_r - 1) + sa.n_r * ang, pb = (long long)sb.n_r * ang;
     const long long npa = sa.npts, npb = sb.npts;
-    // 3+1 quantities of the state at the sphere (the copies are equal)
-    double g[10];
-#pragma unroll
-    for (int q = 0; q < 10; ++q) g[q] = ua[q * npa + pa];
-    const double gxx = g[4], gxy = g[5], gxz = g[6], gyy = g[7], gyz = g[8], gzz = g[9];
-    const double cxx = gyy * gzz - gyz * gyz, cxy = gxz * gyz - gxy * gzz, cxz = gxy * gyz - gxz * gyy;
-    const double cyy = gxx * gzz - gxz * gxz, cyz = gxy * gxz - gxx * gyz, czz = gxx * gyy - gxy * gxy;
-    const double idet = 1.0 / (gxx * cxx + gxy * cxy + gxz * cxz);
-    const double gi[3][3] = {{cxx * idet, cxy * idet, cxz * idet},
-                             {cxy * idet, cyy * idet, cyz * idet},
-                             {cxz * idet, cyz * idet, czz * idet}};
-    const double bl[3] = {g[1], g[2], g[3]};
-    double bu[3];
-#pragma unroll
-    for (int x = 0; x < 3; ++x) bu[x] = gi[x][0] * bl[0] + gi[x][1] * bl[1] + gi[x][2] * bl[2];
-    const double al = sqrt(bu[0] * bl[0] + bu[1] * bl[1] + bu[2] * bl[2] - g[0]);
-    const double st = sa.sth[i], ct = sa.cth[i], sp = sa.sph[j], cp = sa.cph[j];
-    const double xh[3] = {st * cp, st * sp, ct};
-    double su_[3];
-#pragma unroll
-    for (int x = 0; x < 3; ++x) su_[x] = gi[x][0] * xh[0] + gi[x][1] * xh[1] + gi[x][2] * xh[2];
-    const double inorm = 1.0 / sqrt(su_[0] * xh[0] + su_[1] * xh[1] + su_[2] * xh[2]);
-    double sl[3], sup[3];
-#pragma unroll
-    for (int x = 0; x < 3; ++x) {
-        sl[x] = xh[x] * inorm;
-        sup[x] = su_[x] * inorm;
-    }
-    const double b = sl[0] * bu[0] + sl[1] * bu[1] + sl[2] * bu[2];
-    // 0: from a, 1: from b, 0.5: mean (speed 0)
-    auto pick = [](double v) { return v > 0.0 ? 0.0 : (v < 0.0 ? 1.0 : 0.5); };
-    const double wp = pick(al - b), wm = pick(-al - b), wt = pick(-b);
     double co = 1.0, cacc = 0.0;   // stage coefficients of out and acc (RK4, Sec. 2.5)
     if (stage == 1) { co = 0.5 * dt; cacc = dt / 6.0; }
     else if (stage == 2) { co = 0.5 * dt; cacc = dt / 3.0; }
     else if (stage == 3) { co = dt; cacc = dt / 3.0; }
     else if (stage == 4) { co = dt / 6.0; }
-    auto put = [&](int mu, double kp) {
-        const double da = kp - ka[mu * nang + ang], db = kp - kb[mu * nang + ang];
-        const long long oa = mu * npa + pa, ob = mu * npb + pb;
-        if (stage == 0) {
-            out_a[oa] = kp;
-            out_b[ob] = kp;
-            return;
-        }
-        out_a[oa] += co * da;
-        out_b[ob] += co * db;
-        if (cacc != 0.0) {
-            acc_a[oa] += cacc * da;
-            acc_b[ob] += cacc * db;
-        }
-    };
-    for (int q = 0; q < 10; ++q) {
-        double cA[6], cB[6];   // u^0, u^1+, u^1-, u^2_x, u^2_y, u^2_z
-        const double* ks[2] = {ka, kb};
-        double* cs[2] = {cA, cB};
-        for (int side = 0; side < 2; ++side) {
-            const double* kk = ks[side];
-            const double dg = kk[q * nang + ang], dP = kk[(10 + q) * nang + ang];
-            const double dF[3] = {kk[(20 + q) * nang + ang], kk[(30 + q) * nang + ang], kk[(40 + q) * nang + ang]};
-            const double sF = sup[0] * dF[0] + sup[1] * dF[1] + sup[2] * dF[2];
-            double* c = cs[side];
-            c[0] = dg;
-            c[1] = -dg + dP + sF;
-            c[2] = -dg + dP - sF;
+    // the thread's fields, their two raw right-hand sides and stage values
+    constexpr int kF = 8;
+    int mu[kF];
+    int nf;
+    if (q < 10) {
+        nf = 5;
+        mu[0] = q;
+        mu[1] = 10 + q;
+        mu[2] = 20 + q;
+        mu[3] = 30 + q;
+        mu[4] = 40 + q;
+    } else {
+        nf = sa.n_v - 50;
 #pragma unroll
-            for (int x = 0; x < 3; ++x) c[3 + x] = dF[x] - sl[x] * sF;
-        }
-        const double u0 = 0.5 * (cA[0] + cB[0]);
-        const double up = (1.0 - wp) * cA[1] + wp * cB[1];
-        const double um = (1.0 - wm) * cA[2] + wm * cB[2];
-        put(q, u0);
-        put(10 + q, u0 + 0.5 * (up + um));
-#pragma unroll
-        for (int x = 0; x < 3; ++x) put(20 + 10 * x + q, sl[x] * 0.5 * (up - um) + (1.0 - wt) * cA[3 + x] + wt * cB[3 + x]);
+        for (int t = 0; t < kF; ++t) mu[t] = 50 + t;
     }
-    for (int mu = 50; mu < sa.n_v; ++mu) put(mu, 0.5 * (ka[mu * nang + ang] + kb[mu * nang + ang]));
+    double k_a[kF], k_b[kF], oa_[kF], ob_[kF], aa_[kF], ab_[kF];
+#pragma unroll
+    for (int t = 0; t < kF; ++t) {
+        if (t < nf) {
+            k_a[t] = ka[mu[t] * nang + ang];
+            k_b[t] = kb[mu[t] * nang + ang];
+            if (stage != 0) {
+                oa_[t] = out_a[mu[t] * npa + pa];
+                ob_[t] = out_b[mu[t] * npb + pb];
+            }
+            if (cacc != 0.0) {
+                aa_[t] = acc_a[mu[t] * npa + pa];
+                ab_[t] = acc_b[mu[t] * npb + pb];
+            }
+        }
+    }
+    double kp[kF];
+    if (q < 10) {
+        // 3+1 quantities of the state at the sphere (the copies are equal)
+        const int i = (int)(ang % sa.n_th), j = (int)(ang / sa.n_th);
+        double g[10];
+#pragma unroll
+        for (int c = 0; c < 10; ++c) g[c] = ua[c * npa + pa];
+        const double gxx = g[4], gxy = g[5], gxz = g[6], gyy = g[7], gyz = g[8], gzz = g[9];
+        const double cxx = gyy * gzz - gyz * gyz, cxy = gxz * gyz - gxy * gzz, cxz = gxy * gyz - gxz * gyy;
+        const double cyy = gxx * gzz - gxz * gxz, cyz = gxy * gxz - gxx * gyz, czz = gxx * gyy - gxy * gxy;
+        const double idet = 1.0 / (gxx * cxx + gxy * cxy + gxz * cxz);
+        const double gi[3][3] = {{cxx * idet, cxy * idet, cxz * idet},
+                                 {cxy * idet, cyy * idet, cyz * idet},
+                                 {cxz * idet, cyz * idet, czz * idet}};
+        const double bl[3] = {g[1], g[2], g[3]};
+        double bu[3];
+#pragma unroll
+        for (int x = 0; x < 3; ++x) bu[x] = gi[x][0] * bl[0] + gi[x][1] * bl[1] + gi[x][2] * bl[2];
+        const double al = sqrt(bu[0] * bl[0] + bu[1] * bl[1] + bu[2] * bl[2] - g[0]);
+        const double st = sa.sth[i], ct = sa.cth[i], sp = sa.sph[j], cp = sa.cph[j];
+        const double xh[3] = {st * cp, st * sp, ct};
+        double su_[3];
+#pragma unroll
+        for (int x = 0; x < 3; ++x) su_[x] = gi[x][0] * xh[0] + gi[x][1] * xh[1] + gi[x][2] * xh[2];
+        const double inorm = 1.0 / sqrt(su_[0] * xh[0] + su_[1] * xh[1] + su_[2] * xh[2]);
+        double sl[3], sup[3];
+#pragma unroll
+        for (int x = 0; x < 3; ++x) {
+            sl[x] = xh[x] * inorm;
+            sup[x] = su_[x] * inorm;
+        }
+        const double b = sl[0] * bu[0] + sl[1] * bu[1] + sl[2] * bu[2];
+        // 0: from a, 1: from b, 0.5: mean (speed 0)
+        auto pick = [](double v) { return v > 0.0 ? 0.0 : (v < 0.0 ? 1.0 : 0.5); };
+        const double wp = pick(al - b), wm = pick(-al - b), wt = pick(-b);
+        double c2[2][6];   // u^0, u^1+, u^1-, u^2_x, u^2_y, u^2_z of each side
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const double* kk = side ? k_b : k_a;
+            const double dg = kk[0], dP = kk[1];
+            const double dF[3] = {kk[2], kk[3], kk[4]};
+            const double sF = sup[0] * dF[0] + sup[1] * dF[1] + sup[2] * dF[2];
+            c2[side][0] = dg;
+            c2[side][1] = -dg + dP + sF;
+            c2[side][2] = -dg + dP - sF;
+#pragma unroll
+            for (int x = 0; x < 3; ++x) c2[side][3 + x] = dF[x] - sl[x] * sF;
+        }
+        const double u0 = 0.5 * (c2[0][0] + c2[1][0]);
+        const double up = (1.0 - wp) * c2[0][1] + wp * c2[1][1];
+        const double um = (1.0 - wm) * c2[0][2] + wm * c2[1][2];
+        kp[0] = u0;
+        kp[1] = u0 + 0.5 * (up + um);
+#pragma unroll
+        for (int x = 0; x < 3; ++x) kp[2 + x] = sl[x] * 0.5 * (up - um) + (1.0 - wt) * c2[0][3 + x] + wt * c2[1][3 + x];
+    } else {
+#pragma unroll
+        for (int t = 0; t < kF; ++t) kp[t] = 0.5 * (k_a[t] + k_b[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < kF; ++t) {
+        if (t >= nf) continue;
+        const long long oa = mu[t] * npa + pa, ob = mu[t] * npb + pb;
+        if (stage == 0) {
+            out_a[oa] = kp[t];
+            out_b[ob] = kp[t];
+            continue;
+        }
+        const double da = kp[t] - k_a[t], db = kp[t] - k_b[t];
+        out_a[oa] = oa_[t] + co * da;
+        out_b[ob] = ob_[t] + co * db;
+        if (cacc != 0.0) {
+            acc_a[oa] = aa_[t] + cacc * da;
+            acc_b[ob] = ab_[t] + cacc * db;
+        }
+    }
 }
 
 __global__ __launch_bounds__(256) void k_finite(const double* __restrict__ u, size_t n, int* flag) {
@@ -742,8 +782,9 @@ hipError_t launch_patch(const KShell& a, const KShell& b, const double* ua, cons
                         double* out_a, double* acc_a, double* out_b, double* acc_b, double dt, int stage,
                         hipStream_t st) {
     const long long nang = (long long)a.n_th * a.n_ph;
-    hipLaunchKernelGGL(k_patch, dim3((unsigned)((nang + 255) / 256)), dim3(256), 0, st, a, b, ua, ka, kb, out_a,
-                       acc_a, out_b, acc_b, dt, stage);
+    if (a.n_v != 50 && a.n_v != 58) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_patch, dim3((unsigned)((nang + 255) / 256), a.n_v == 58 ? 11u : 10u), dim3(256), 0, st, a, b,
+                       ua, ka, kb, out_a, acc_a, out_b, acc_b, dt, stage);
     return hipGetLastError();
 }
 
