@@ -492,7 +492,7 @@ def main():
                 gm.close()
                 del um, gm
                 torch.cuda.empty_cache()
-        # the survey's next rows, measured: nested shells (four 33x32x64 shells
+        # beside the hot path, measured: nested shells (four 33x32x64 shells
         # on [1.8, 17.8] coupled at their shared spheres against the same four
         # shells uncoupled) and the scalar Y and graded Yg filters on the
         # 33x32x64 shell against Yn
