@@ -4,7 +4,8 @@ fields of App. A.2): the patch is a change of basis into characteristic
 fields and back (equal inputs pass unchanged), it takes every field from its
 upwind side, and a shell split in two at a shared sphere converges to the
 single shell's evolution with resolution (a patch that ignores the upwind
-direction does not)."""
+direction does not), and a static black hole split in two stays static to
+truncation error."""
 import numpy as np
 import pytest
 
@@ -82,11 +83,12 @@ def test_patch_follows_the_sign_of_the_speed():
     assert np.abs(_chars(out, u, xhat)[1] - _chars(rB, u, xhat)[1]).max() < 1e-12
 
 
-def _evolve_split(n, T, patch=None):
+def _evolve_split(n, T, patch=None, amp=1e-3, drift=False):
     """Perturbed Kerr-Schild on [1.8, 11.8]: two shells [1.8, 6.8] + [6.8, 11.8]
     with n radial points each, and one shell with 2n - 1 (whose middle point
     is r = 6.8); both to time T with the same steps.  Returns the state on
-    the sphere r = 6.8 of each."""
+    the sphere r = 6.8 of each (drift: the largest change of the state since
+    t = 0 on the single shell and on the split pair instead)."""
     n_th, n_ph = 6, 12
     outer = Shell(2 * n - 1, n_th, n_ph, 1.8, 11.8)
     parts = [Shell(n, n_th, n_ph, 1.8, 6.8), Shell(n, n_th, n_ph, 6.8, 11.8)]
@@ -95,7 +97,7 @@ def _evolve_split(n, T, patch=None):
     dt = T / steps
 
     def init(sh):
-        g10 = inputs.perturbed_kerr_schild(7, sh.r, sh.theta, sh.phi, amp=1e-3)
+        g10 = inputs.perturbed_kerr_schild(7, sh.r, sh.theta, sh.phi, amp=amp)
         u = oid.first_order_data(g10, sh)
         return (u,) + oid.static_gauge(u, sh)
 
@@ -105,6 +107,7 @@ def _evolve_split(n, T, patch=None):
     ps = [init(s) for s in parts]
     nev = nested.NestedEvolution(parts, 50, [p[1] for p in ps], [p[2] for p in ps], "Yn", 2)
     us = [p[0] for p in ps]
+    u10, us0 = u1.copy(), [u.copy() for u in us]
     if patch is not None:
         nested.patch_interface, saved = patch, nested.patch_interface
     try:
@@ -114,6 +117,8 @@ def _evolve_split(n, T, patch=None):
     finally:
         if patch is not None:
             nested.patch_interface = saved
+    if drift:
+        return np.abs(u1 - u10).max(), max(np.abs(u - u0).max() for u, u0 in zip(us, us0))
     return u1[..., n - 1], us[0][..., -1], us[1][..., 0], us[0][..., 0] - u1[..., 0]
 
 
@@ -146,3 +151,21 @@ def test_convergence_pin_catches_a_wrong_patch(mistake):
     single, a, _, _ = _evolve_split(11, 1.0, patch=wrong)
     good_single, good_a, _, _ = _evolve_split(11, 1.0)
     assert np.abs(a - single).max() > 100 * np.abs(good_a - good_single).max()
+
+
+@pytest.mark.slow
+def test_static_black_hole_stays_static_across_the_interface():
+    """Unperturbed Kerr-Schild is a static solution: split at r = 6.8 it
+    drifts only by truncation error, which falls exponentially with the
+    radial points (measured 3.2e-2 at 7, 1.5e-3 at 11 points per shell by
+    t = 1; the single shell with 13 and 21 points: 5.0e-3, 2.5e-5, its
+    points clustering twice as densely at the horizon), while a patch that
+    takes every field from the inside shell or from its downwind side drives
+    the interface (9.2e-2 and 0.24 at 11 points)."""
+    single7, split7 = _evolve_split(7, 1.0, amp=0.0, drift=True)
+    single11, split11 = _evolve_split(11, 1.0, amp=0.0, drift=True)
+    assert split11 < 0.1 * split7 and single11 < 0.1 * single7
+    correct = nested.patch_interface
+    for wrong in (lambda rA, rB, u_pt, xhat: rA.copy(), lambda rA, rB, u_pt, xhat: correct(rB, rA, u_pt, xhat)):
+        _, bad = _evolve_split(11, 1.0, patch=wrong, amp=0.0, drift=True)
+        assert bad > 30 * split11, (bad, split11)
